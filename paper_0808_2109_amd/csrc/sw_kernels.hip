@@ -1,0 +1,595 @@
+// sw_kernels.hip -- the HIP kernels of the sweep and their host launchers.
+//
+// Plain path: one launch per phase and replica (K1, K2, K3, and for PCC the
+// candidate, coverage and feedback kernels), each a grid of workgroups that
+// walk contiguous chunks of tiles.  Batched path: one persistent kernel runs
+// every phase of many sweeps for all replicas, with a software grid barrier
+// between phases.
+#include "sw_device.hpp"
+#include "sw_internal.hpp"
+
+namespace sw {
+
+// tile shapes: (id, dim, TX, TY, TZ)
+#define SW_SHAPES_2D(X) X(0, 2, 64, 32, 1) X(1, 2, 64, 16, 1) X(2, 2, 64, 64, 1) X(3, 2, 128, 16, 1) X(4, 2, 32, 32, 1)
+#define SW_SHAPES_3D(X) X(0, 3, 32, 8, 8) X(1, 3, 16, 16, 8) X(2, 3, 64, 4, 8) X(3, 3, 32, 16, 4) X(4, 3, 16, 8, 8)
+#define SW_SHAPES(X) SW_SHAPES_2D(X) SW_SHAPES_3D(X)
+
+constexpr int kNumShapes = 5;
+
+// XCD-aware chunking: workgroup b runs on XCD b % 8.  Giving XCD k the k-th
+// eighth of the (replica, tile) work list keeps a band of neighbouring tiles
+// (whose halos and labels are shared) inside one XCD's L2.
+__device__ __forceinline__ void chunk_of(int nitems, int& i0, int& i1)
+{
+    const int G = gridDim.x;
+    const int b = blockIdx.x;
+    const int lam = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+    i0 = (int)(((int64_t)lam * nitems) / G);
+    i1 = (int)(((int64_t)(lam + 1) * nitems) / G);
+}
+
+__device__ __forceinline__ void block_sum2(int64_t& a, int64_t& b, int64_t* red)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off, 64);
+        b += __shfl_down(b, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        red[2 * wave] = a;
+        red[2 * wave + 1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = b = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            a += red[2 * w];
+            b += red[2 * w + 1];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Plain kernels.
+// ---------------------------------------------------------------------------
+template <class C>
+__global__ __launch_bounds__(kBlock) void k1_kernel(const SwRep* Rd, uint32_t s, int64_t* em)
+{
+    __shared__ K1Smem<C> sm;
+    __shared__ int64_t red[2 * kBlock / 64];
+    const SwRep R = *Rd;
+    int t0, t1;
+    chunk_of(R.ntiles, t0, t1);
+    int64_t e = 0, m = 0;
+    for (int t = t0; t < t1; ++t) k1_tile<C>(R, t, s, R.thr, sm, em != nullptr, e, m);
+    if (em) {
+        block_sum2(e, m, red);
+        if (threadIdx.x == 0 && t1 > t0) {
+            atomicAdd((unsigned long long*)&em[0], (unsigned long long)e);
+            atomicAdd((unsigned long long*)&em[1], (unsigned long long)m);
+        }
+    }
+}
+
+template <class C>
+__global__ __launch_bounds__(kBlock) void k2_kernel(const SwRep* Rd, uint32_t s)
+{
+    const SwRep R = *Rd;
+    int t0, t1;
+    chunk_of(R.ntiles, t0, t1);
+    for (int t = t0; t < t1; ++t) k2_tile<C>(R, t, s);
+}
+
+template <class C>
+__global__ __launch_bounds__(kBlock) void k3_kernel(const SwRep* Rd, uint32_t s)
+{
+    const SwRep R = *Rd;
+    int t0, t1;
+    chunk_of(R.ntiles, t0, t1);
+    for (int t = t0; t < t1; ++t) k3_tile<C>(R, t, s);
+}
+
+template <class C>
+__global__ __launch_bounds__(kBlock) void kcand_kernel(const SwRep* Rd, uint32_t s)
+{
+    const SwRep R = *Rd;
+    int t0, t1;
+    chunk_of(R.ntiles, t0, t1);
+    for (int t = t0; t < t1; ++t) k_cand_tile<C>(R, t, s);
+}
+
+// coverage test of the candidates' bitmaps (slots [c0, c1) of every axis);
+// the bitmaps are cleared for the next sweep
+__device__ void perc_chunk(const SwRep& R, uint32_t c0, uint32_t c1, int* local_flag)
+{
+    const uint32_t L = (uint32_t)R.L;
+    const uint32_t bw = (L + 31u) / 32u;
+    const uint32_t nslots = (R.dim == 3) ? L * L : L;
+    const uint32_t tailbits = L & 31u;
+    const uint32_t tailmask = tailbits ? ((1u << tailbits) - 1u) : 0xFFFFFFFFu;
+    for (int a = 0; a < R.dim; ++a) {
+        for (uint32_t c = c0 + threadIdx.x; c < c1; c += kBlock) {
+            uint32_t* bm = R.bmp + ((size_t)a * nslots + c) * bw;
+            bool full = true;
+            for (uint32_t w = 0; w < bw; ++w) {
+                const uint32_t v = bm[w];
+                const uint32_t want = (w == bw - 1) ? tailmask : 0xFFFFFFFFu;
+                full = full && ((v & want) == want);
+                if (v) bm[w] = 0;
+            }
+            if (full) *local_flag = 1;
+        }
+    }
+}
+
+__device__ void pcc_update(SwRep* Rd, uint32_t s)
+{
+    const int perc = *Rd->pflag;
+    *Rd->pflag = 0;
+    const double dp = ldexp(Rd->dp0, -(int)(s / Rd->halve_every));
+    double q = perc ? (Rd->p - dp) : (Rd->p + dp);
+    if (q < 0.0) q = 0.0;
+    if (q > 1.0) q = 1.0;
+    Rd->p = q;
+    uint64_t thr;
+    if (!(q > 0.0)) thr = 0;
+    else if (q >= 1.0) thr = 4294967296ull;
+    else thr = (uint64_t)floor(ldexp(q, 32));
+    Rd->thr = thr;
+    if (s < Rd->trace_cap) {
+        Rd->perc_trace[s] = perc;
+        Rd->p_trace[s] = q;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void kperc_kernel(const SwRep* Rd)
+{
+    __shared__ int flag;
+    const SwRep R = *Rd;
+    if (threadIdx.x == 0) flag = 0;
+    __syncthreads();
+    const uint32_t nslots = (R.dim == 3) ? (uint32_t)R.L * (uint32_t)R.L : (uint32_t)R.L;
+    const uint32_t per = (nslots + gridDim.x - 1) / gridDim.x;
+    const uint32_t c0 = min(nslots, blockIdx.x * per), c1 = min(nslots, c0 + per);
+    perc_chunk(R, c0, c1, &flag);
+    __syncthreads();
+    if (threadIdx.x == 0 && flag) atomicOr(R.pflag, 1);
+}
+
+__global__ void kpcc_update_kernel(SwRep* Rd, uint32_t s)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) pcc_update(Rd, s);
+}
+
+// E_int and M of the current configuration, reading neighbours from memory
+__device__ void measure_range(const SwRep& R, uint32_t i0, uint32_t i1, uint32_t stride, int64_t& e, int64_t& m)
+{
+    const uint32_t L = (uint32_t)R.L;
+    const uint32_t LL = L * L;
+    for (uint32_t i = i0; i < i1; i += stride) {
+        const int sv = R.spins[i];
+        const uint32_t x = i % L;
+        const uint32_t y = (i / L) % L;
+        int nb = R.spins[(x == L - 1) ? i - (L - 1) : i + 1];
+        nb += R.spins[(y == L - 1) ? i - (L - 1) * L : i + L];
+        if (R.dim == 3) {
+            const uint32_t z = i / LL;
+            nb += R.spins[(z == L - 1) ? i - (L - 1) * LL : i + LL];
+        }
+        m += sv;
+        e += sv * nb;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void kmeasure_kernel(const SwRep* Rd, int64_t* dst)
+{
+    __shared__ int64_t red[2 * kBlock / 64];
+    const SwRep R = *Rd;
+    int64_t e = 0, m = 0;
+    measure_range(R, blockIdx.x * kBlock + threadIdx.x, R.N, gridDim.x * kBlock, e, m);
+    block_sum2(e, m, red);
+    if (threadIdx.x == 0) {
+        atomicAdd((unsigned long long*)&dst[0], (unsigned long long)e);
+        atomicAdd((unsigned long long*)&dst[1], (unsigned long long)m);
+    }
+}
+
+// initial spins: site i is up when bit i%32 of word (i>>5)%4 of Philox(i>>7, 0, 0, INIT) is set
+__global__ __launch_bounds__(kBlock) void kinit_kernel(const SwRep* Rd)
+{
+    const SwRep R = *Rd;
+    const uint32_t nblk = (R.N + 127u) / 128u;
+    for (uint32_t b = blockIdx.x * kBlock + threadIdx.x; b < nblk; b += gridDim.x * kBlock) {
+        const U4 r = philox10(b, 0u, 0u, kTagInit, (uint32_t)R.seed, (uint32_t)(R.seed >> 32));
+        for (uint32_t k = 0; k < 128u; ++k) {
+            const uint32_t i = b * 128u + k;
+            if (i >= R.N) break;
+            R.spins[i] = ((pick(r, k >> 5) >> (k & 31u)) & 1u) ? (int8_t)1 : (int8_t)-1;
+        }
+    }
+}
+
+__global__ void kset_state_kernel(SwRep* Rd, uint32_t sweep, uint32_t measured, double p, uint64_t thr, int set_p)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        Rd->sweep = sweep;
+        Rd->measured = measured;
+        if (set_p) {
+            Rd->p = p;
+            Rd->thr = thr;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batched engine.
+// ---------------------------------------------------------------------------
+template <class C>
+struct SmemSize {
+    static constexpr size_t v = sizeof(K1Smem<C>);
+};
+
+#define SW_SMEM_MAX(id, D, X, Y, Z) (SmemSize<TileCfg<D, X, Y, Z>>::v),
+constexpr size_t smem_sizes[] = {SW_SHAPES(SW_SMEM_MAX) 0};
+constexpr size_t cmax(const size_t* a, int n) { return n == 0 ? 0 : (a[0] > cmax(a + 1, n - 1) ? a[0] : cmax(a + 1, n - 1)); }
+constexpr size_t kEngineSmem = cmax(smem_sizes, 2 * kNumShapes);
+
+// grid barrier: arrival counter + generation; bounded wait so that a grid
+// that is not fully co-resident aborts instead of hanging
+__device__ bool grid_barrier(EngineCtl* ctl, uint64_t timeout_ticks)
+{
+    __shared__ int aborted;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned g = __hip_atomic_load(&ctl->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned arrived =
+            __hip_atomic_fetch_add(&ctl->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        int ab = __hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == gridDim.x - 1) {
+            __hip_atomic_store(&ctl->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctl->gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const uint64_t t0 = wall_clock64();
+            while (!ab && __hip_atomic_load(&ctl->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(2);
+                if (wall_clock64() - t0 > timeout_ticks) {
+                    __hip_atomic_store(&ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ab = 1;
+                }
+                ab = ab || __hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        aborted = ab;
+    }
+    __syncthreads();
+    return aborted == 0;
+}
+
+// replica r runs sweep R.sweep + it in this launch when it is below its target
+__device__ __forceinline__ bool rep_runs(const SwRep& R, int it, int n_sweeps, uint32_t& s)
+{
+    if (!R.active) return false;
+    const uint64_t target = min((uint64_t)R.sweep + (uint64_t)n_sweeps, (uint64_t)R.limit);
+    s = R.sweep + (uint32_t)it;
+    return (uint64_t)s < target;
+}
+
+#define SW_DISPATCH_CASE(id, D, X, Y, Z, CALL) \
+    case (D * 16 + id): {                      \
+        using C = TileCfg<D, X, Y, Z>;         \
+        CALL;                                  \
+        break;                                 \
+    }
+
+__global__ __launch_bounds__(kBlock) void kengine_kernel(SwRep* reps, const EngineItem* items, int nitems,
+                                                         EngineCtl* ctl, int n_sweeps, int any_pcc,
+                                                         int any_series, uint64_t timeout_ticks)
+{
+    __shared__ __align__(16) char smem[kEngineSmem];
+    __shared__ int64_t red[2 * kBlock / 64];
+    __shared__ int pflag_local;
+    int i0, i1;
+    chunk_of(nitems, i0, i1);
+
+    for (int it = 0; it < n_sweeps; ++it) {
+        // ---- K1: bonds + tile labelling (+ E, M of the incoming configuration)
+        {
+            int cur = -1;
+            int64_t e = 0, m = 0;
+            int64_t* dst = nullptr;
+            for (int i = i0; i <= i1; ++i) {
+                const int rep = (i < i1) ? items[i].rep : -2;
+                if (rep != cur) {
+                    // flush the sums of the previous replica
+                    if (cur >= 0 && dst) {
+                        int64_t ee = e, mm = m;
+                        block_sum2(ee, mm, red);
+                        if (threadIdx.x == 0) {
+                            atomicAdd((unsigned long long*)&dst[0], (unsigned long long)ee);
+                            atomicAdd((unsigned long long*)&dst[1], (unsigned long long)mm);
+                        }
+                    }
+                    e = m = 0;
+                    dst = nullptr;
+                    cur = rep;
+                    if (rep >= 0) {
+                        const SwRep& R = reps[rep];
+                        uint32_t s;
+                        if (rep_runs(R, it, n_sweeps, s) && (R.flags & FLAG_SERIES) && s >= 1 &&
+                            (it > 0 || R.measured < R.sweep))
+                            dst = R.series + 2 * (size_t)(s - 1);
+                    }
+                }
+                if (i == i1) break;
+                const SwRep R = reps[rep];
+                uint32_t s;
+                if (!rep_runs(R, it, n_sweeps, s)) continue;
+                switch (R.dim * 16 + R.shape) {
+#define SW_K1_CASE(id, D, X, Y, Z) \
+    SW_DISPATCH_CASE(id, D, X, Y, Z, (k1_tile<C>(R, items[i].tile, s, R.thr, *reinterpret_cast<K1Smem<C>*>(smem), dst != nullptr, e, m)))
+                    SW_SHAPES(SW_K1_CASE)
+                    default: break;
+                }
+            }
+        }
+        if (!grid_barrier(ctl, timeout_ticks)) return;
+        // ---- K2: border merge + flip table
+        for (int i = i0; i < i1; ++i) {
+            const SwRep R = reps[items[i].rep];
+            uint32_t s;
+            if (!rep_runs(R, it, n_sweeps, s)) continue;
+            switch (R.dim * 16 + R.shape) {
+#define SW_K2_CASE(id, D, X, Y, Z) SW_DISPATCH_CASE(id, D, X, Y, Z, (k2_tile<C>(R, items[i].tile, s)))
+                SW_SHAPES(SW_K2_CASE)
+                default: break;
+            }
+        }
+        if (!grid_barrier(ctl, timeout_ticks)) return;
+        // ---- PCC: percolation candidates
+        if (any_pcc) {
+            for (int i = i0; i < i1; ++i) {
+                const SwRep R = reps[items[i].rep];
+                uint32_t s;
+                if (!(R.flags & FLAG_PCC) || !rep_runs(R, it, n_sweeps, s)) continue;
+                switch (R.dim * 16 + R.shape) {
+#define SW_KC_CASE(id, D, X, Y, Z) SW_DISPATCH_CASE(id, D, X, Y, Z, (k_cand_tile<C>(R, items[i].tile, s)))
+                    SW_SHAPES(SW_KC_CASE)
+                    default: break;
+                }
+            }
+            if (!grid_barrier(ctl, timeout_ticks)) return;
+        }
+        // ---- K3: cluster flip (+ coverage marks)
+        for (int i = i0; i < i1; ++i) {
+            const SwRep R = reps[items[i].rep];
+            uint32_t s;
+            if (!rep_runs(R, it, n_sweeps, s)) continue;
+            switch (R.dim * 16 + R.shape) {
+#define SW_K3_CASE(id, D, X, Y, Z) SW_DISPATCH_CASE(id, D, X, Y, Z, (k3_tile<C>(R, items[i].tile, s)))
+                SW_SHAPES(SW_K3_CASE)
+                default: break;
+            }
+        }
+        if (!grid_barrier(ctl, timeout_ticks)) return;
+        // ---- PCC: coverage test, then feedback on p
+        if (any_pcc) {
+            for (int i = i0; i < i1; ++i) {
+                const SwRep R = reps[items[i].rep];
+                uint32_t s;
+                if (!(R.flags & FLAG_PCC) || !rep_runs(R, it, n_sweeps, s)) continue;
+                const uint32_t nslots = (R.dim == 3) ? (uint32_t)R.L * (uint32_t)R.L : (uint32_t)R.L;
+                const int t = items[i].tile;
+                const uint32_t c0 = (uint32_t)(((uint64_t)t * nslots) / (uint32_t)R.ntiles);
+                const uint32_t c1 = (uint32_t)(((uint64_t)(t + 1) * nslots) / (uint32_t)R.ntiles);
+                if (threadIdx.x == 0) pflag_local = 0;
+                __syncthreads();
+                perc_chunk(R, c0, c1, &pflag_local);
+                __syncthreads();
+                if (threadIdx.x == 0 && pflag_local) atomicOr(R.pflag, 1);
+            }
+            if (!grid_barrier(ctl, timeout_ticks)) return;
+            for (int i = i0; i < i1; ++i) {
+                SwRep* Rp = &reps[items[i].rep];
+                uint32_t s;
+                if (items[i].tile != 0 || !(Rp->flags & FLAG_PCC) || !rep_runs(*Rp, it, n_sweeps, s)) continue;
+                if (threadIdx.x == 0) pcc_update(Rp, s);
+            }
+            if (!grid_barrier(ctl, timeout_ticks)) return;
+        }
+    }
+
+    // ---- E, M after the last sweep of every recording replica
+    if (any_series) {
+        int cur = -1;
+        int64_t e = 0, m = 0;
+        int64_t* dst = nullptr;
+        for (int i = i0; i <= i1; ++i) {
+            const int rep = (i < i1) ? items[i].rep : -2;
+            if (rep != cur) {
+                if (cur >= 0 && dst) {
+                    int64_t ee = e, mm = m;
+                    block_sum2(ee, mm, red);
+                    if (threadIdx.x == 0) {
+                        atomicAdd((unsigned long long*)&dst[0], (unsigned long long)ee);
+                        atomicAdd((unsigned long long*)&dst[1], (unsigned long long)mm);
+                    }
+                }
+                e = m = 0;
+                dst = nullptr;
+                cur = rep;
+                if (rep >= 0) {
+                    const SwRep& R = reps[rep];
+                    const uint64_t target = min((uint64_t)R.sweep + (uint64_t)n_sweeps, (uint64_t)R.limit);
+                    if (R.active && (R.flags & FLAG_SERIES) && target >= 1 && R.measured < target)
+                        dst = R.series + 2 * (size_t)(target - 1);
+                }
+            }
+            if (i == i1) break;
+            if (!dst) continue;
+            const SwRep R = reps[rep];
+            // the tile's share of the site range
+            const uint32_t a0 = (uint32_t)(((uint64_t)items[i].tile * R.N) / (uint32_t)R.ntiles);
+            const uint32_t a1 = (uint32_t)(((uint64_t)(items[i].tile + 1) * R.N) / (uint32_t)R.ntiles);
+            measure_range(R, a0 + threadIdx.x, a1, kBlock, e, m);
+        }
+    }
+    if (!grid_barrier(ctl, timeout_ticks)) return;
+
+    // ---- advance the counters (no workgroup reads them after the barriers above)
+    if (blockIdx.x == 0) {
+        const int nrep = ctl->nreps;
+        for (int r = threadIdx.x; r < nrep; r += kBlock) {
+            SwRep* Rp = &reps[r];
+            if (!Rp->active) continue;
+            const uint64_t target = min((uint64_t)Rp->sweep + (uint64_t)n_sweeps, (uint64_t)Rp->limit);
+            if (Rp->flags & FLAG_SERIES) Rp->measured = (uint32_t)max((uint64_t)Rp->measured, target);
+            Rp->sweep = (uint32_t)target;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+// ---------------------------------------------------------------------------
+static int grid_for(int ntiles, int per_cu)
+{
+    const int cus = device_cu_count();
+    int g = cus * per_cu;
+    if (ntiles < g) g = ntiles;
+    if (g >= 8) g -= g % 8;
+    return g < 1 ? 1 : g;
+}
+
+#define SW_LAUNCH_CASE(id, D, X, Y, Z, KERNEL, ...)                                                    \
+    case (D * 16 + id): {                                                                               \
+        using C = TileCfg<D, X, Y, Z>;                                                                  \
+        hipLaunchKernelGGL(KERNEL<C>, dim3(grid), dim3(kBlock), 0, stream, __VA_ARGS__);                \
+        break;                                                                                          \
+    }
+
+int launch_k1(const SwRep& h, SwRep* d, uint32_t s, int64_t* em, hipStream_t stream, int per_cu)
+{
+    const int grid = grid_for(h.ntiles, per_cu);
+    switch (h.dim * 16 + h.shape) {
+#define L1(id, D, X, Y, Z) SW_LAUNCH_CASE(id, D, X, Y, Z, k1_kernel, d, s, em)
+        SW_SHAPES(L1)
+        default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_k2(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream, int per_cu)
+{
+    const int grid = grid_for(h.ntiles, per_cu);
+    switch (h.dim * 16 + h.shape) {
+#define L2(id, D, X, Y, Z) SW_LAUNCH_CASE(id, D, X, Y, Z, k2_kernel, d, s)
+        SW_SHAPES(L2)
+        default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_k3(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream, int per_cu)
+{
+    const int grid = grid_for(h.ntiles, per_cu);
+    switch (h.dim * 16 + h.shape) {
+#define L3(id, D, X, Y, Z) SW_LAUNCH_CASE(id, D, X, Y, Z, k3_kernel, d, s)
+        SW_SHAPES(L3)
+        default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_cand(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream)
+{
+    const int grid = grid_for(h.ntiles, 4);
+    switch (h.dim * 16 + h.shape) {
+#define LC(id, D, X, Y, Z) SW_LAUNCH_CASE(id, D, X, Y, Z, kcand_kernel, d, s)
+        SW_SHAPES(LC)
+        default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_perc(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream)
+{
+    const uint32_t nslots = (h.dim == 3) ? (uint32_t)h.L * (uint32_t)h.L : (uint32_t)h.L;
+    int grid = (int)((nslots + kBlock - 1) / kBlock);
+    if (grid > 2048) grid = 2048;
+    hipLaunchKernelGGL(kperc_kernel, dim3(grid), dim3(kBlock), 0, stream, d);
+    hipLaunchKernelGGL(kpcc_update_kernel, dim3(1), dim3(64), 0, stream, d, s);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_measure(const SwRep& h, SwRep* d, int64_t* dst, hipStream_t stream)
+{
+    int grid = (int)((h.N + kBlock - 1) / kBlock);
+    const int cap = device_cu_count() * 8;
+    if (grid > cap) grid = cap;
+    hipLaunchKernelGGL(kmeasure_kernel, dim3(grid), dim3(kBlock), 0, stream, d, dst);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_init(const SwRep& h, SwRep* d, hipStream_t stream)
+{
+    const uint32_t nblk = (h.N + 127u) / 128u;
+    int grid = (int)((nblk + kBlock - 1) / kBlock);
+    if (grid > 4096) grid = 4096;
+    hipLaunchKernelGGL(kinit_kernel, dim3(grid), dim3(kBlock), 0, stream, d);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_set_state(SwRep* d, uint32_t sweep, uint32_t measured, double p, uint64_t thr, int set_p,
+                     hipStream_t stream)
+{
+    hipLaunchKernelGGL(kset_state_kernel, dim3(1), dim3(64), 0, stream, d, sweep, measured, p, thr, set_p);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int engine_grid_limit()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kengine_kernel, kBlock, 0) != hipSuccess) return -1;
+    return nb * device_cu_count();
+}
+
+int launch_engine(SwRep* reps, const EngineItem* items, int nitems, EngineCtl* ctl, int n_sweeps, int any_pcc,
+                  int any_series, int grid, uint64_t timeout_ticks, hipStream_t stream)
+{
+    hipLaunchKernelGGL(kengine_kernel, dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, ctl, n_sweeps,
+                       any_pcc, any_series, timeout_ticks);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int shape_count(int dim)
+{
+    (void)dim;
+    return kNumShapes;
+}
+
+int shape_extents(int dim, int id, int* tx, int* ty, int* tz)
+{
+#define SW_EXT(i, D, X, Y, Z)          \
+    if (dim == D && id == i) {         \
+        *tx = X;                       \
+        *ty = Y;                       \
+        *tz = Z;                       \
+        return 0;                      \
+    }
+    SW_SHAPES(SW_EXT)
+    return -1;
+}
+
+int shape_xwords(int dim, int id)
+{
+#define SW_XW(i, D, X, Y, Z) \
+    if (dim == D && id == i) return TileCfg<D, X, Y, Z>::XW;
+    SW_SHAPES(SW_XW)
+    return -1;
+}
+
+}  // namespace sw

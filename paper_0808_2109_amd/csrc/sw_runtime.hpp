@@ -1,0 +1,78 @@
+// sw_runtime.hpp -- host-side handle layout shared by the runtime, the
+// autotuner and the job server (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "../../include/sw_api.h"
+#include "sw_device.hpp"
+#include "sw_internal.hpp"
+
+namespace sw {
+
+struct ReplicaH {
+    sw_params prm{};
+    SwRep h{};               // host mirror of the device descriptor
+    bool own_spins = true;
+    bool labels_valid = false;
+};
+
+struct TimedLaunch {
+    int phase;
+    hipEvent_t a, b;
+};
+
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+uint64_t threshold_from_p(double p);
+int validate_params(const sw_params* p);
+uint64_t nsites_of(const sw_params* p);
+int default_shape(int dim);
+void fill_geometry(SwRep& h, int shape);
+uint64_t footprint_bytes(const sw_params* p, int shape);
+int replica_alloc(ReplicaH& r, const sw_params* p, int shape, hipStream_t stream);
+void replica_free(ReplicaH& r);
+
+}  // namespace sw
+
+struct sw_lattice {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int mode = SW_MODE_PLAIN;
+    int per_cu[3] = {8, 8, 8};          // plain-kernel workgroups per CU (K1, K2, K3)
+    std::vector<sw::ReplicaH> reps;
+    sw::SwRep* d_reps = nullptr;        // device descriptor array
+    bool mirror_stale = false;          // device-side counters changed since the last read
+    // timing
+    bool timing = false;
+    std::vector<sw::TimedLaunch> pending;
+    std::vector<hipEvent_t> event_pool;
+    double ms[6] = {0, 0, 0, 0, 0, 0};
+    int64_t launches[6] = {0, 0, 0, 0, 0, 0};
+    // persistent engine
+    sw::EngineItem* items = nullptr;
+    size_t items_cap = 0;
+    int nitems = 0;
+    bool items_dirty = true;
+    sw::EngineCtl* ctl = nullptr;
+    int engine_grid_limit = 0;
+    int engine_grid_cap = 0;            // 0: occupancy limit
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int graph_n = -1;
+    int graph_grid = -1;
+    int graph_flags = -1;
+};
+
+namespace sw {
+int handle_sync(sw_lattice* h);
+int sync_mirror(sw_lattice* h);
+int push_desc(sw_lattice* h, int r);
+int ensure_capacity(sw_lattice* h, int r, uint64_t need);
+int plain_sweep(sw_lattice* h, int r, int32_t n);
+int batched_sweep(sw_lattice* h, int32_t n);
+int timing_collect(sw_lattice* h);
+}  // namespace sw

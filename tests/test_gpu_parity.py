@@ -1,0 +1,186 @@
+"""Parity of the HIP sweep with the CPU oracle (GPU; calls go through the C ABI).
+
+Spins and canonical labels must equal the oracle's bit for bit after every
+compared sweep, and the (E_int, M) series must be integer-exact.  Sizes span
+several tiles with ragged tails in every axis, every compiled tile shape, the
+degenerate bond probabilities p = 0 and p = 1, and the full workload sizes.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_0808_2109_amd import swgpu, workloads
+
+pytestmark = pytest.mark.gpu
+
+TC = workloads.TC_2D
+
+
+def _lattice(dim, L, seed, T=None, p=-1.0, series=True, keep=True):
+    prm = swgpu.make_params(dim, L, T=T, seed=seed, p_bond=p, series=series, keep_labels=keep)
+    return swgpu.Lattice(prm)
+
+
+def _oracle_thr(T=None, p=-1.0):
+    return oracle.threshold(1.0, T) if p < 0 else oracle.threshold_from_p(p)
+
+
+def _step_compare(lat, dim, L, seed, thr, spins, sweeps, s0=0):
+    """Sweep one at a time, comparing spins and labels with the oracle each time."""
+    for k in range(sweeps):
+        lat.sweep(1)
+        spins, lab = oracle.sweep(dim, L, seed, s0 + k, thr, spins)
+        got_lab = lat.labels()
+        got_sp = lat.spins()
+        assert np.array_equal(got_lab, lab), f"labels differ after sweep {s0 + k} (dim={dim} L={L})"
+        assert np.array_equal(got_sp, spins), f"spins differ after sweep {s0 + k} (dim={dim} L={L})"
+    return spins
+
+
+@pytest.mark.parametrize("dim,L", [(2, 64), (2, 37), (3, 16), (3, 13)])
+def test_initial_spins_and_threshold(dim, L):
+    T = TC if dim == 2 else workloads.TC_3D
+    with _lattice(dim, L, 7, T=T) as lat:
+        assert np.array_equal(lat.spins(), oracle.init_spins(dim, L, 7))
+        s, p, thr = lat.state()
+        assert s == 0 and thr == oracle.threshold(1.0, T)
+        assert lat.measure() == oracle.measure(dim, L, oracle.init_spins(dim, L, 7))
+
+
+SIZES_2D = [3, 5, 17, 63, 64, 65, 100, 130, 257]
+SIZES_3D = [3, 7, 16, 33, 40]
+
+
+@pytest.mark.parametrize("L", SIZES_2D)
+def test_sweeps_2d_ragged(L):
+    seed = 1000 + L
+    with _lattice(2, L, seed, T=TC) as lat:
+        thr = lat.state()[2]
+        assert thr == _oracle_thr(TC)
+        _step_compare(lat, 2, L, seed, thr, oracle.init_spins(2, L, seed), 4)
+
+
+@pytest.mark.parametrize("L", SIZES_3D)
+def test_sweeps_3d_ragged(L):
+    seed = 2000 + L
+    T = workloads.TC_3D
+    with _lattice(3, L, seed, T=T) as lat:
+        thr = lat.state()[2]
+        _step_compare(lat, 3, L, seed, thr, oracle.init_spins(3, L, seed), 3)
+
+
+@pytest.mark.parametrize("dim,L,p", [(2, 70, 0.0), (2, 70, 1.0), (3, 20, 0.0), (3, 20, 1.0), (2, 96, 0.2),
+                                     (2, 96, 0.9), (3, 24, 0.6)])
+def test_degenerate_and_extreme_p(dim, L, p):
+    seed = 31
+    with _lattice(dim, L, seed, p=p) as lat:
+        thr = lat.state()[2]
+        assert thr == oracle.threshold_from_p(p)
+        spins = workloads.random_spins(dim, L, seed)
+        lat.set_spins(0, spins)
+        spins = _step_compare(lat, dim, L, seed, thr, spins, 2)
+        if p == 0.0:
+            assert np.array_equal(lat.labels(), np.arange(L ** dim, dtype=np.int32))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_every_tile_shape_gives_identical_results(dim):
+    L = 100 if dim == 2 else 27
+    T = TC if dim == 2 else workloads.TC_3D
+    seed = 77
+    thr = _oracle_thr(T)
+    ref_sp, ref_lab = oracle.sweep(dim, L, seed, 0, thr, oracle.init_spins(dim, L, seed))
+    ref_sp2, ref_lab2 = oracle.sweep(dim, L, seed, 1, thr, ref_sp)
+    for shape in range(len(swgpu.tile_shapes(dim))):
+        with _lattice(dim, L, seed, T=T) as lat:
+            lat.set_tile_shape(0, shape)
+            lat.sweep(1)
+            assert np.array_equal(lat.labels(), ref_lab), f"shape {shape}"
+            assert np.array_equal(lat.spins(), ref_sp), f"shape {shape}"
+            lat.sweep(1)
+            assert np.array_equal(lat.labels(), ref_lab2), f"shape {shape}"
+            assert np.array_equal(lat.spins(), ref_sp2), f"shape {shape}"
+
+
+def test_parity_workload_1000_sweeps_series_exact():
+    """2D L=64 at T_c, seed 1, 1000 sweeps, (E_int, M) recorded after every sweep."""
+    wl = workloads.parity()
+    rep = wl.replicas[0]
+    prm = swgpu.params_from_replica(rep, series=True, keep_labels=True)
+    thr = oracle.threshold(1.0, rep.T)
+    spins = oracle.init_spins(2, rep.L, rep.seed)
+    with swgpu.Lattice(prm) as lat:
+        done = 0
+        for chunk in (1, 9, 90, 400, 500):
+            lat.sweep(chunk)
+            ref = oracle.run(2, rep.L, rep.seed, chunk, thr=thr, s0=done, spins=spins)
+            spins = ref["spins"]
+            done += chunk
+            assert np.array_equal(lat.spins(), spins), f"spins differ after {done} sweeps"
+            assert np.array_equal(lat.labels(), ref["labels"]), f"labels differ after {done} sweeps"
+        full = oracle.run(2, rep.L, rep.seed, wl.sweeps, thr=thr)
+        series = lat.series()
+        assert series.shape == (wl.sweeps, 2)
+        assert np.array_equal(series, full["series"])
+        assert lat.measure() == tuple(full["series"][-1])
+
+
+def test_series_across_calls_and_measure():
+    dim, L, seed = 2, 48, 5
+    with _lattice(2, L, seed, T=2.0) as lat:
+        thr = lat.state()[2]
+        for n in (3, 1, 0, 4):
+            lat.sweep(n)
+        ref = oracle.run(dim, L, seed, 8, thr=thr)
+        assert np.array_equal(lat.series(), ref["series"])
+
+
+def test_checkpoint_resume_is_bit_exact():
+    dim, L, seed, T = 2, 80, 9, 2.4
+    with _lattice(dim, L, seed, T=T) as a:
+        a.sweep(7)
+        straight = a.spins()
+        straight_series = a.series()
+    with _lattice(dim, L, seed, T=T) as b:
+        b.sweep(4)
+        ckpt = b.spins()
+    with _lattice(dim, L, seed, T=T) as c:
+        c.set_spins(0, ckpt, sweep=4)
+        c.sweep(3)
+        assert np.array_equal(c.spins(), straight)
+        assert np.array_equal(c.series()[4:], straight_series[4:])
+
+
+@pytest.mark.parametrize("dim,L,T", [(2, 8192, TC), (3, 256, workloads.TC_3D)])
+def test_full_size_first_sweeps(dim, L, T):
+    """The plain workload's lattices at full size: two sweeps, every site compared."""
+    seed = 1
+    with _lattice(dim, L, seed, T=T) as lat:
+        thr = lat.state()[2]
+        spins = oracle.init_spins(dim, L, seed)
+        assert np.array_equal(lat.spins(), spins)
+        _step_compare(lat, dim, L, seed, thr, spins, 2)
+
+
+def test_plain_full_size_later_sweep_properties():
+    """8192^2 after 20 sweeps: properties that hold for any correct sweep.
+
+    Labels are canonical (label <= index, label[label] = label), every open
+    bond of the sweep joins equal labels and every site carries its cluster's
+    drawn spin; the oracle then recomputes sweep 20 from the GPU's state 19.
+    """
+    dim, L, seed = 2, 8192, 1
+    with _lattice(dim, L, seed, T=TC) as lat:
+        lat.sweep(19)
+        s19 = lat.spins()
+        lat.sweep(1)
+        thr = lat.state()[2]
+        ref_sp, ref_lab = oracle.sweep(dim, L, seed, 19, thr, s19)
+        lab = lat.labels()
+        assert np.array_equal(lab, ref_lab)
+        assert np.array_equal(lat.spins(), ref_sp)
+        idx = np.arange(L * L, dtype=np.int64)
+        assert np.all(lab <= idx)
+        assert np.array_equal(lab[lab], lab)
