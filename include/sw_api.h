@@ -180,6 +180,9 @@ int sw_get_timing(sw_lattice* h, double* ms, int64_t* launches, int32_t n);
  * sw_tile_shapes(). */
 int sw_set_tile_shape(sw_lattice* h, int32_t replica, int32_t shape);
 
+/* Tile shape currently used by a replica (index into sw_tile_shapes()). */
+int sw_get_tile_shape(sw_lattice* h, int32_t replica, int32_t* shape);
+
 /* Number of compiled tile shapes and their extents (tx, ty, tz; tz = 1 in 2D). */
 int sw_tile_shapes(int32_t dim, int32_t* count, int32_t* tx, int32_t* ty, int32_t* tz, int32_t cap);
 

@@ -877,6 +877,15 @@ int sw_set_tile_shape(sw_lattice* h, int32_t replica, int32_t shape)
     return push_desc(h, replica);
 }
 
+int sw_get_tile_shape(sw_lattice* h, int32_t replica, int32_t* shape)
+{
+    int rc = check_rep(h, replica);
+    if (rc) return rc;
+    if (!shape) return fail(SW_EINVAL, "null output");
+    *shape = h->reps[replica].h.shape;
+    return SW_OK;
+}
+
 int sw_tile_shapes(int32_t dim, int32_t* count, int32_t* tx, int32_t* ty, int32_t* tz, int32_t cap)
 {
     if (dim != 2 && dim != 3) return fail(SW_EINVAL, "dim must be 2 or 3");

@@ -87,6 +87,7 @@ def lib():
         "sw_set_timing": (c.c_int, [vp, c.c_int32]),
         "sw_get_timing": (c.c_int, [vp, P(c.c_double), P(c.c_int64), c.c_int32]),
         "sw_set_tile_shape": (c.c_int, [vp, c.c_int32, c.c_int32]),
+        "sw_get_tile_shape": (c.c_int, [vp, c.c_int32, P(c.c_int32)]),
         "sw_tile_shapes": (c.c_int, [c.c_int32, P(c.c_int32), P(c.c_int32), P(c.c_int32), P(c.c_int32), c.c_int32]),
         "sw_autotune": (c.c_int, [vp, c.c_int32, c.c_char_p]),
         "sw_free": (c.c_int, [vp]),
@@ -262,6 +263,11 @@ class Lattice:
     # -- tuning / timing
     def set_tile_shape(self, r: int, shape: int):
         _check(lib().sw_set_tile_shape(self._h, r, shape))
+
+    def tile_shape(self, r: int = 0) -> int:
+        s = ctypes.c_int32()
+        _check(lib().sw_get_tile_shape(self._h, r, ctypes.byref(s)))
+        return int(s.value)
 
     def autotune(self, sweeps: int = 3, cache: Optional[str] = None):
         _check(lib().sw_autotune(self._h, sweeps, cache.encode() if cache else None))
