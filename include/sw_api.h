@@ -8,8 +8,8 @@
  *   2. sites joined by a path of bonds form a cluster;
  *   3. every cluster takes one fresh random spin, shared by all its sites.
  * On top of the plain sweep the library runs the probability-changing-cluster
- * feedback of Sec. III (extension rule, periodic boundaries), many replicas in
- * one persistent launch, and a continuous-batching job server.
+ * feedback of Sec. III (extension rule, periodic boundaries), many replicas
+ * swept together by one hipGraph launch, and a continuous-batching job server.
  *
  * Conventions shared by every entry point
  *   - Lattices are periodic, dim 2 or 3, N = L^dim sites, site index
@@ -70,7 +70,8 @@ enum {
 /* execution modes of a multi-replica handle (sw_set_mode) */
 enum {
     SW_MODE_PLAIN = 0,    /* one launch sequence per replica and sweep            */
-    SW_MODE_BATCHED = 1   /* all replicas in one persistent launch (hipGraph)     */
+    SW_MODE_BATCHED = 1   /* all replicas' tiles in each phase launch, the sweeps
+                             of one call replayed as one hipGraph                 */
 };
 
 /*
@@ -171,8 +172,8 @@ int sw_set_timing(sw_lattice* h, int32_t enable);
 /*
  * Accumulated device time per phase since timing was enabled: ms[k] and
  * launches[k] for k < n (k = 0 bond+tile labelling, 1 border merge + flip
- * table, 2 cluster flip, 3 percolation + feedback, 4 measurement, 5 persistent
- * batch kernel).  Synchronises.
+ * table, 2 cluster flip, 3 percolation + feedback, 4 measurement, 5 batched
+ * sweeps: one replayed graph per call, all phases together).  Synchronises.
  */
 int sw_get_timing(sw_lattice* h, double* ms, int64_t* launches, int32_t n);
 
@@ -188,7 +189,7 @@ int sw_tile_shapes(int32_t dim, int32_t* count, int32_t* tx, int32_t* ty, int32_
 
 /*
  * Autotune: for every (dim, size class) present in the handle, time each
- * compiled tile shape (and the persistent grid size) on scratch copies for
+ * compiled tile shape (and, for batches, the workgroups per CU) on scratch copies for
  * `sweeps` sweeps and keep the fastest.  Results are written to / read from
  * the JSON cache at `cache_path` (NULL: no cache).  Trajectories do not
  * depend on the choice.  Synchronises.

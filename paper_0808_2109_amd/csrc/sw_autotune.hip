@@ -1,10 +1,15 @@
-// sw_autotune.hip -- tile-shape and persistent-grid autotuner.
+// sw_autotune.hip -- tile-shape and batched-grid autotuner.
 //
 // Results never depend on the tile shape or the grid (every union hooks to
-// the smaller root), so the tuner is free to pick whatever runs fastest.  For
-// each (dim, size class = floor(log2 L)) present in a handle it times every
-// compiled tile shape on a scratch lattice with the same parameters, and for
-// the persistent engine the workgroups per CU; choices are cached as JSON.
+// the smaller root), so the tuner is free to pick whatever runs fastest.
+//   one replica:   every compiled tile shape is timed with plain launches on
+//                  a scratch lattice with the same parameters;
+//   many replicas: every batched variant (a 2D and a 3D shape) and three
+//                  grid sizes are timed on a scratch copy of all
+//                  replicas in batched mode.
+// Choices are cached as JSON keyed by (arch, dim, size class = floor(log2 L))
+// for single lattices and by (arch, "batch", replica count, total sites) for
+// batches.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -18,11 +23,6 @@
 
 namespace sw {
 
-struct TuneKey {
-    int dim, lclass;
-    bool operator<(const TuneKey& o) const { return dim != o.dim ? dim < o.dim : lclass < o.lclass; }
-};
-
 static int size_class(int L)
 {
     int c = 0;
@@ -30,17 +30,10 @@ static int size_class(int L)
     return c;
 }
 
-static std::string key_string(const TuneKey& k)
+// minimal reader for the cache this file writes: {"key": {"shape": s, "grid": g, ...}, ...}
+static std::map<std::string, std::pair<int, int>> read_cache(const char* path)
 {
-    char buf[64];
-    snprintf(buf, sizeof(buf), "gfx950:d%d:l%d", k.dim, k.lclass);
-    return buf;
-}
-
-// minimal reader for the cache this file writes: {"key": {"shape": s, "ms": t}, ...}
-static std::map<std::string, int> read_cache(const char* path)
-{
-    std::map<std::string, int> out;
+    std::map<std::string, std::pair<int, int>> out;
     if (!path) return out;
     FILE* f = fopen(path, "rb");
     if (!f) return out;
@@ -55,54 +48,142 @@ static std::map<std::string, int> read_cache(const char* path)
         if (end == std::string::npos) break;
         const std::string key = txt.substr(pos + 1, end - pos - 1);
         const size_t sp = txt.find("\"shape\":", end);
-        if (sp == std::string::npos) break;
-        out[key] = atoi(txt.c_str() + sp + 8);
+        const size_t gp = txt.find("\"grid\":", end);
+        if (sp == std::string::npos || gp == std::string::npos) break;
+        out[key] = {atoi(txt.c_str() + sp + 8), atoi(txt.c_str() + gp + 7)};
         pos = end + 1;
     }
     return out;
 }
 
-static void write_cache(const char* path, const std::map<std::string, std::pair<int, double>>& entries)
+struct Choice {
+    int shape, grid;
+    double ms;
+};
+
+static void write_cache(const char* path, const std::map<std::string, Choice>& entries)
 {
     if (!path) return;
+    auto old = read_cache(path);
+    std::map<std::string, Choice> all;
+    for (auto& kv : old) all[kv.first] = Choice{kv.second.first, kv.second.second, -1.0};
+    for (auto& kv : entries) all[kv.first] = kv.second;
     FILE* f = fopen(path, "wb");
     if (!f) return;
     fprintf(f, "{\n");
     size_t i = 0;
-    for (auto& kv : entries) {
-        fprintf(f, "  \"%s\": {\"shape\": %d, \"ms_per_sweep\": %.6f}%s\n", kv.first.c_str(), kv.second.first,
-                kv.second.second, (++i < entries.size()) ? "," : "");
+    for (auto& kv : all) {
+        fprintf(f, "  \"%s\": {\"shape\": %d, \"grid\": %d, \"ms_per_sweep\": %.6f}%s\n", kv.first.c_str(),
+                kv.second.shape, kv.second.grid, kv.second.ms, (++i < all.size()) ? "," : "");
     }
     fprintf(f, "}\n");
     fclose(f);
 }
 
-// milliseconds per sweep of a scratch single-replica lattice with this shape
-static int time_shape(const sw_params& prm, int shape, int sweeps, hipStream_t stream, double* ms_out)
+// milliseconds per sweep of `sweeps` sweeps on handle s (after one untimed sweep)
+static int time_sweeps(sw_lattice* s, int sweeps, double* ms_out)
 {
-    sw_params p = prm;
-    p.flags &= ~(uint32_t)SW_RECORD_SERIES;
-    sw_lattice* h = nullptr;
-    int rc = sw_init(&p, 1, -1, stream, &h);
+    int rc = sw_sweep(s, 1);
+    if (!rc) rc = handle_sync(s);
     if (rc) return rc;
-    rc = sw_set_tile_shape(h, 0, shape);
-    if (!rc) rc = sw_sweep(h, 1);                      // warm-up
-    if (!rc) rc = handle_sync(h);
     hipEvent_t a = nullptr, b = nullptr;
-    if (!rc && (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)) rc = fail(SW_EHIP, "event");
-    if (!rc) {
-        hipEventRecord(a, h->stream);
-        rc = sw_sweep(h, sweeps);
-        hipEventRecord(b, h->stream);
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        if (a) hipEventDestroy(a);
+        return fail(SW_EHIP, "event creation failed");
     }
-    if (!rc) rc = handle_sync(h);
+    hipEventRecord(a, s->stream);
+    rc = sw_sweep(s, sweeps);
+    hipEventRecord(b, s->stream);
+    if (!rc) rc = handle_sync(s);
     float ms = 0.f;
-    if (!rc && hipEventElapsedTime(&ms, a, b) != hipSuccess) rc = fail(SW_EHIP, "event timing");
-    if (a) hipEventDestroy(a);
-    if (b) hipEventDestroy(b);
-    sw_free(h);
+    if (!rc && hipEventElapsedTime(&ms, a, b) != hipSuccess) rc = fail(SW_EHIP, "event timing failed");
+    hipEventDestroy(a);
+    hipEventDestroy(b);
     if (!rc) *ms_out = ms / sweeps;
     return rc;
+}
+
+static int tune_single(sw_lattice* h, int32_t sweeps, const char* cache_path)
+{
+    ReplicaH& rep = h->reps[0];
+    char key[64];
+    snprintf(key, sizeof(key), "gfx950:d%d:l%d", rep.h.dim, size_class(rep.h.L));
+    auto cached = read_cache(cache_path);
+    auto it = cached.find(key);
+    if (it != cached.end() && it->second.first >= 0 && it->second.first < shape_count(rep.h.dim))
+        return sw_set_tile_shape(h, 0, it->second.first);
+    sw_params p = rep.prm;
+    p.flags &= ~(uint32_t)SW_RECORD_SERIES;
+    int best = default_shape(p.dim);
+    double best_ms = 1e30;
+    for (int shape = 0; shape < shape_count(p.dim); ++shape) {
+        sw_lattice* s = nullptr;
+        int rc = sw_init(&p, 1, -1, h->stream, &s);
+        if (!rc) rc = sw_set_tile_shape(s, 0, shape);
+        double ms = 0;
+        if (!rc) rc = time_sweeps(s, sweeps, &ms);
+        if (s) sw_free(s);
+        if (rc) return rc;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = shape;
+        }
+    }
+    std::map<std::string, Choice> out;
+    out[key] = Choice{best, 0, best_ms};
+    write_cache(cache_path, out);
+    return sw_set_tile_shape(h, 0, best);
+}
+
+static int tune_batch(sw_lattice* h, int32_t sweeps, const char* cache_path)
+{
+    uint64_t total = 0;
+    for (auto& r : h->reps) total += r.h.N;
+    char key[96];
+    snprintf(key, sizeof(key), "gfx950:batch:r%zu:n%llu", h->reps.size(), (unsigned long long)total);
+    int best_v = 0, best_grid = 0;
+    double best_ms = 1e30;
+    auto cached = read_cache(cache_path);
+    auto it = cached.find(key);
+    if (it != cached.end() && it->second.first >= 0 && it->second.first < shape_count(2)) {
+        best_v = it->second.first;
+        best_grid = it->second.second;
+    } else {
+        std::vector<sw_params> ps;
+        for (auto& r : h->reps) {
+            sw_params p = r.prm;
+            p.flags &= ~(uint32_t)SW_RECORD_SERIES;
+            ps.push_back(p);
+        }
+        for (int v = 0; v < shape_count(2); ++v) {
+            sw_lattice* s = nullptr;
+            int rc = sw_init(ps.data(), (int32_t)ps.size(), -1, h->stream, &s);
+            for (size_t r = 0; r < ps.size() && !rc; ++r) rc = sw_set_tile_shape(s, (int32_t)r, v);
+            if (!rc) s->mode = SW_MODE_BATCHED;
+            for (int per_cu : {4, 8, 16}) {
+                if (rc) break;
+                s->batch_per_cu = per_cu;
+                double ms = 0;
+                rc = time_sweeps(s, sweeps, &ms);
+                if (!rc && ms < best_ms) {
+                    best_ms = ms;
+                    best_v = v;
+                    best_grid = per_cu;
+                }
+            }
+            if (s) sw_free(s);
+            if (rc) return rc;
+        }
+        std::map<std::string, Choice> out;
+        out[key] = Choice{best_v, best_grid, best_ms};
+        write_cache(cache_path, out);
+    }
+    for (size_t r = 0; r < h->reps.size(); ++r) {
+        int rc = sw_set_tile_shape(h, (int32_t)r, best_v);
+        if (rc) return rc;
+    }
+    if (best_grid > 0) h->batch_per_cu = best_grid;
+    return SW_OK;
 }
 
 }  // namespace sw
@@ -113,88 +194,8 @@ extern "C" int sw_autotune(sw_lattice* h, int32_t sweeps, const char* cache_path
 {
     if (!h) return fail(SW_EINVAL, "null handle");
     if (sweeps < 1) return fail(SW_EINVAL, "need at least one timed sweep");
+    if (hipSetDevice(h->device) != hipSuccess) return fail(SW_EHIP, "hipSetDevice failed");
     int rc = sync_mirror(h);
     if (rc) return rc;
-    std::map<TuneKey, int> rep_of;                       // representative replica per class
-    for (size_t r = 0; r < h->reps.size(); ++r) {
-        const TuneKey k{h->reps[r].h.dim, size_class(h->reps[r].h.L)};
-        if (!rep_of.count(k) || h->reps[r].h.L > h->reps[rep_of[k]].h.L) rep_of[k] = (int)r;
-    }
-    auto cached = read_cache(cache_path);
-    std::map<std::string, std::pair<int, double>> out;
-    std::map<TuneKey, int> choice;
-    for (auto& kv : rep_of) {
-        const std::string ks = key_string(kv.first);
-        if (cached.count(ks) && cached[ks] >= 0 && cached[ks] < shape_count(kv.first.dim)) {
-            choice[kv.first] = cached[ks];
-            out[ks] = {cached[ks], -1.0};
-            continue;
-        }
-        const sw_params& prm = h->reps[kv.second].prm;
-        int best = default_shape(prm.dim);
-        double best_ms = 1e30;
-        for (int s = 0; s < shape_count(prm.dim); ++s) {
-            double ms = 0;
-            rc = time_shape(prm, s, sweeps, h->stream, &ms);
-            if (rc) return rc;
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = s;
-            }
-        }
-        choice[kv.first] = best;
-        out[ks] = {best, best_ms};
-    }
-    for (size_t r = 0; r < h->reps.size(); ++r) {
-        const TuneKey k{h->reps[r].h.dim, size_class(h->reps[r].h.L)};
-        rc = sw_set_tile_shape(h, (int32_t)r, choice[k]);
-        if (rc) return rc;
-    }
-    // persistent engine: workgroups per CU, timed on a scratch copy of all replicas
-    if (h->reps.size() > 1) {
-        const int limit = engine_grid_limit();
-        if (limit > 0) {
-            const int cus = device_cu_count();
-            std::vector<sw_params> ps;
-            for (auto& r : h->reps) {
-                sw_params p = r.prm;
-                p.flags &= ~(uint32_t)SW_RECORD_SERIES;
-                ps.push_back(p);
-            }
-            sw_lattice* s = nullptr;
-            rc = sw_init(ps.data(), (int32_t)ps.size(), -1, h->stream, &s);
-            if (rc) return rc;
-            for (size_t r = 0; r < ps.size() && !rc; ++r) rc = sw_set_tile_shape(s, (int32_t)r, h->reps[r].h.shape);
-            s->mode = SW_MODE_BATCHED;
-            double best_ms = 1e30;
-            int best_cap = 0;
-            for (int cap : {limit, std::max(cus, limit / 2), std::max(cus, limit / 4)}) {
-                if (rc) break;
-                s->engine_grid_cap = cap;
-                rc = sw_sweep(s, 1);                      // capture + warm-up
-                if (!rc) rc = handle_sync(s);
-                if (rc) break;
-                hipEvent_t a = nullptr, b = nullptr;
-                hipEventCreate(&a);
-                hipEventCreate(&b);
-                hipEventRecord(a, s->stream);
-                rc = sw_sweep(s, 1);
-                hipEventRecord(b, s->stream);
-                if (!rc) rc = handle_sync(s);
-                float ms = 0.f;
-                if (!rc) hipEventElapsedTime(&ms, a, b);
-                hipEventDestroy(a);
-                hipEventDestroy(b);
-                if (!rc && ms < best_ms) {
-                    best_ms = ms;
-                    best_cap = cap;
-                }
-            }
-            sw_free(s);
-            if (rc) return rc;
-            h->engine_grid_cap = best_cap;
-        }
-    }
-    write_cache(cache_path, out);
-    return SW_OK;
+    return h->reps.size() == 1 ? tune_single(h, sweeps, cache_path) : tune_batch(h, sweeps, cache_path);
 }

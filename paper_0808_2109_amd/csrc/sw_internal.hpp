@@ -14,13 +14,6 @@ struct EngineItem {
     int32_t tile;
 };
 
-struct EngineCtl {
-    unsigned count;   // workgroups arrived at the current barrier
-    unsigned gen;     // barrier generation
-    int abort;        // set when a barrier wait timed out
-    int nreps;        // replicas in the descriptor array
-};
-
 int device_cu_count();
 uint64_t device_wallclock_hz();
 
@@ -33,9 +26,10 @@ int launch_measure(const SwRep& h, SwRep* d, int64_t* dst, hipStream_t stream);
 int launch_init(const SwRep& h, SwRep* d, hipStream_t stream);
 int launch_set_state(SwRep* d, uint32_t sweep, uint32_t measured, double p, uint64_t thr, int set_p,
                      hipStream_t stream);
-int engine_grid_limit();
-int launch_engine(SwRep* reps, const EngineItem* items, int nitems, EngineCtl* ctl, int n_sweeps, int any_pcc,
-                  int any_series, int grid, uint64_t timeout_ticks, hipStream_t stream);
+// enqueue n sweeps of every active replica as batched phase launches (used
+// under stream capture to build the batch graph)
+int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, int nitems, int n_sweeps, int any_pcc,
+                 int any_series, int grid, hipStream_t stream);
 
 int shape_count(int dim);
 int shape_extents(int dim, int id, int* tx, int* ty, int* tz);

@@ -2,20 +2,30 @@
 //
 // Plain path: one launch per phase and replica (K1, K2, K3, and for PCC the
 // candidate, coverage and feedback kernels), each a grid of workgroups that
-// walk contiguous chunks of tiles.  Batched path: one persistent kernel runs
-// every phase of many sweeps for all replicas, with a software grid barrier
-// between phases.
+// walk contiguous chunks of tiles.  Batched path: each phase is one launch
+// over the tiles of all replicas, and the launches of many sweeps are replayed
+// from one hipGraph.
 #include "sw_device.hpp"
 #include "sw_internal.hpp"
 
 namespace sw {
 
-// tile shapes: (id, dim, TX, TY, TZ)
-#define SW_SHAPES_2D(X) X(0, 2, 64, 32, 1) X(1, 2, 64, 16, 1) X(2, 2, 64, 64, 1) X(3, 2, 128, 16, 1) X(4, 2, 32, 32, 1)
-#define SW_SHAPES_3D(X) X(0, 3, 32, 8, 8) X(1, 3, 16, 16, 8) X(2, 3, 64, 4, 8) X(3, 3, 32, 16, 4) X(4, 3, 16, 8, 8)
+// tile shapes: (id, dim, TX, TY, TZ).  The batched kernels are compiled for
+// the pairs (2D shape i, 3D shape i).
+#define SW_SHAPES_2D(X) X(0, 2, 64, 32, 1) X(1, 2, 64, 16, 1) X(2, 2, 64, 64, 1) X(3, 2, 32, 32, 1)
+#define SW_SHAPES_3D(X) X(0, 3, 32, 8, 8) X(1, 3, 32, 16, 4) X(2, 3, 64, 4, 8) X(3, 3, 32, 4, 16)
 #define SW_SHAPES(X) SW_SHAPES_2D(X) SW_SHAPES_3D(X)
+using Eng0_2D = TileCfg<2, 64, 32, 1>;
+using Eng0_3D = TileCfg<3, 32, 8, 8>;
+using Eng1_2D = TileCfg<2, 64, 16, 1>;
+using Eng1_3D = TileCfg<3, 32, 16, 4>;
+using Eng2_2D = TileCfg<2, 64, 64, 1>;
+using Eng2_3D = TileCfg<3, 64, 4, 8>;
+using Eng3_2D = TileCfg<2, 32, 32, 1>;
+using Eng3_3D = TileCfg<3, 32, 4, 16>;
+#define SW_ENGINE_PAIRS(X) X(0, Eng0_2D, Eng0_3D) X(1, Eng1_2D, Eng1_3D) X(2, Eng2_2D, Eng2_3D) X(3, Eng3_2D, Eng3_3D)
 
-constexpr int kNumShapes = 5;
+constexpr int kNumShapes = 4;
 
 // XCD-aware chunking: workgroup b runs on XCD b % 8.  Giving XCD k the k-th
 // eighth of the (replica, tile) work list keeps a band of neighbouring tiles
@@ -85,10 +95,11 @@ __global__ __launch_bounds__(kBlock) void k2_kernel(const SwRep* Rd, uint32_t s)
 template <class C>
 __global__ __launch_bounds__(kBlock) void k3_kernel(const SwRep* Rd, uint32_t s)
 {
+    __shared__ K3Smem<C> sm;
     const SwRep R = *Rd;
     int t0, t1;
     chunk_of(R.ntiles, t0, t1);
-    for (int t = t0; t < t1; ++t) k3_tile<C>(R, t, s);
+    for (int t = t0; t < t1; ++t) k3_tile<C>(R, t, s, sm);
 }
 
 template <class C>
@@ -124,20 +135,25 @@ __device__ void perc_chunk(const SwRep& R, uint32_t c0, uint32_t c1, int* local_
     }
 }
 
+// PCC feedback after sweep s: p -/+ dp, dp = dp0 * 2^-(s / halve_every),
+// clamped to [0, 1]; the next sweep's threshold follows from p
 __device__ void pcc_update(SwRep* Rd, uint32_t s)
 {
-    const int perc = *Rd->pflag;
-    *Rd->pflag = 0;
+    const int perc = __hip_atomic_exchange(Rd->pflag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const double dp = ldexp(Rd->dp0, -(int)(s / Rd->halve_every));
-    double q = perc ? (Rd->p - dp) : (Rd->p + dp);
+    const double p = __longlong_as_double(
+        (long long)__hip_atomic_load((unsigned long long*)&Rd->p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    double q = perc ? (p - dp) : (p + dp);
     if (q < 0.0) q = 0.0;
     if (q > 1.0) q = 1.0;
-    Rd->p = q;
     uint64_t thr;
     if (!(q > 0.0)) thr = 0;
     else if (q >= 1.0) thr = 4294967296ull;
     else thr = (uint64_t)floor(ldexp(q, 32));
-    Rd->thr = thr;
+    __hip_atomic_store((unsigned long long*)&Rd->p, (unsigned long long)__double_as_longlong(q), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store((unsigned long long*)&Rd->thr, (unsigned long long)thr, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
     if (s < Rd->trace_cap) {
         Rd->perc_trace[s] = perc;
         Rd->p_trace[s] = q;
@@ -224,52 +240,13 @@ __global__ void kset_state_kernel(SwRep* Rd, uint32_t sweep, uint32_t measured, 
 }
 
 // ---------------------------------------------------------------------------
-// Persistent batched engine.
+constexpr size_t cmax2(size_t a, size_t b) { return a > b ? a : b; }
+
+// Batched execution: every phase of a sweep is one launch over the (replica,
+// tile) work list of all replicas; a hipGraph holds the launches of n sweeps.
+// Kernel boundaries order the phases, so no software grid barrier is needed.
 // ---------------------------------------------------------------------------
-template <class C>
-struct SmemSize {
-    static constexpr size_t v = sizeof(K1Smem<C>);
-};
-
-#define SW_SMEM_MAX(id, D, X, Y, Z) (SmemSize<TileCfg<D, X, Y, Z>>::v),
-constexpr size_t smem_sizes[] = {SW_SHAPES(SW_SMEM_MAX) 0};
-constexpr size_t cmax(const size_t* a, int n) { return n == 0 ? 0 : (a[0] > cmax(a + 1, n - 1) ? a[0] : cmax(a + 1, n - 1)); }
-constexpr size_t kEngineSmem = cmax(smem_sizes, 2 * kNumShapes);
-
-// grid barrier: arrival counter + generation; bounded wait so that a grid
-// that is not fully co-resident aborts instead of hanging
-__device__ bool grid_barrier(EngineCtl* ctl, uint64_t timeout_ticks)
-{
-    __shared__ int aborted;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const unsigned g = __hip_atomic_load(&ctl->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned arrived =
-            __hip_atomic_fetch_add(&ctl->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        int ab = __hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == gridDim.x - 1) {
-            __hip_atomic_store(&ctl->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctl->gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            const uint64_t t0 = wall_clock64();
-            while (!ab && __hip_atomic_load(&ctl->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                __builtin_amdgcn_s_sleep(2);
-                if (wall_clock64() - t0 > timeout_ticks) {
-                    __hip_atomic_store(&ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ab = 1;
-                }
-                ab = ab || __hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        aborted = ab;
-    }
-    __syncthreads();
-    return aborted == 0;
-}
-
-// replica r runs sweep R.sweep + it in this launch when it is below its target
+// replica r runs sweep R.sweep + it in this graph when it is below its target
 __device__ __forceinline__ bool rep_runs(const SwRep& R, int it, int n_sweeps, uint32_t& s)
 {
     if (!R.active) return false;
@@ -278,180 +255,176 @@ __device__ __forceinline__ bool rep_runs(const SwRep& R, int it, int n_sweeps, u
     return (uint64_t)s < target;
 }
 
-#define SW_DISPATCH_CASE(id, D, X, Y, Z, CALL) \
-    case (D * 16 + id): {                      \
-        using C = TileCfg<D, X, Y, Z>;         \
-        CALL;                                  \
-        break;                                 \
-    }
-
-__global__ __launch_bounds__(kBlock) void kengine_kernel(SwRep* reps, const EngineItem* items, int nitems,
-                                                         EngineCtl* ctl, int n_sweeps, int any_pcc,
-                                                         int any_series, uint64_t timeout_ticks)
+__device__ __forceinline__ void flush_em(int64_t e, int64_t m, int64_t* dst, int64_t* red)
 {
-    __shared__ __align__(16) char smem[kEngineSmem];
-    __shared__ int64_t red[2 * kBlock / 64];
-    __shared__ int pflag_local;
-    int i0, i1;
-    chunk_of(nitems, i0, i1);
-
-    for (int it = 0; it < n_sweeps; ++it) {
-        // ---- K1: bonds + tile labelling (+ E, M of the incoming configuration)
-        {
-            int cur = -1;
-            int64_t e = 0, m = 0;
-            int64_t* dst = nullptr;
-            for (int i = i0; i <= i1; ++i) {
-                const int rep = (i < i1) ? items[i].rep : -2;
-                if (rep != cur) {
-                    // flush the sums of the previous replica
-                    if (cur >= 0 && dst) {
-                        int64_t ee = e, mm = m;
-                        block_sum2(ee, mm, red);
-                        if (threadIdx.x == 0) {
-                            atomicAdd((unsigned long long*)&dst[0], (unsigned long long)ee);
-                            atomicAdd((unsigned long long*)&dst[1], (unsigned long long)mm);
-                        }
-                    }
-                    e = m = 0;
-                    dst = nullptr;
-                    cur = rep;
-                    if (rep >= 0) {
-                        const SwRep& R = reps[rep];
-                        uint32_t s;
-                        if (rep_runs(R, it, n_sweeps, s) && (R.flags & FLAG_SERIES) && s >= 1 &&
-                            (it > 0 || R.measured < R.sweep))
-                            dst = R.series + 2 * (size_t)(s - 1);
-                    }
-                }
-                if (i == i1) break;
-                const SwRep R = reps[rep];
-                uint32_t s;
-                if (!rep_runs(R, it, n_sweeps, s)) continue;
-                switch (R.dim * 16 + R.shape) {
-#define SW_K1_CASE(id, D, X, Y, Z) \
-    SW_DISPATCH_CASE(id, D, X, Y, Z, (k1_tile<C>(R, items[i].tile, s, R.thr, *reinterpret_cast<K1Smem<C>*>(smem), dst != nullptr, e, m)))
-                    SW_SHAPES(SW_K1_CASE)
-                    default: break;
-                }
-            }
-        }
-        if (!grid_barrier(ctl, timeout_ticks)) return;
-        // ---- K2: border merge + flip table
-        for (int i = i0; i < i1; ++i) {
-            const SwRep R = reps[items[i].rep];
-            uint32_t s;
-            if (!rep_runs(R, it, n_sweeps, s)) continue;
-            switch (R.dim * 16 + R.shape) {
-#define SW_K2_CASE(id, D, X, Y, Z) SW_DISPATCH_CASE(id, D, X, Y, Z, (k2_tile<C>(R, items[i].tile, s)))
-                SW_SHAPES(SW_K2_CASE)
-                default: break;
-            }
-        }
-        if (!grid_barrier(ctl, timeout_ticks)) return;
-        // ---- PCC: percolation candidates
-        if (any_pcc) {
-            for (int i = i0; i < i1; ++i) {
-                const SwRep R = reps[items[i].rep];
-                uint32_t s;
-                if (!(R.flags & FLAG_PCC) || !rep_runs(R, it, n_sweeps, s)) continue;
-                switch (R.dim * 16 + R.shape) {
-#define SW_KC_CASE(id, D, X, Y, Z) SW_DISPATCH_CASE(id, D, X, Y, Z, (k_cand_tile<C>(R, items[i].tile, s)))
-                    SW_SHAPES(SW_KC_CASE)
-                    default: break;
-                }
-            }
-            if (!grid_barrier(ctl, timeout_ticks)) return;
-        }
-        // ---- K3: cluster flip (+ coverage marks)
-        for (int i = i0; i < i1; ++i) {
-            const SwRep R = reps[items[i].rep];
-            uint32_t s;
-            if (!rep_runs(R, it, n_sweeps, s)) continue;
-            switch (R.dim * 16 + R.shape) {
-#define SW_K3_CASE(id, D, X, Y, Z) SW_DISPATCH_CASE(id, D, X, Y, Z, (k3_tile<C>(R, items[i].tile, s)))
-                SW_SHAPES(SW_K3_CASE)
-                default: break;
-            }
-        }
-        if (!grid_barrier(ctl, timeout_ticks)) return;
-        // ---- PCC: coverage test, then feedback on p
-        if (any_pcc) {
-            for (int i = i0; i < i1; ++i) {
-                const SwRep R = reps[items[i].rep];
-                uint32_t s;
-                if (!(R.flags & FLAG_PCC) || !rep_runs(R, it, n_sweeps, s)) continue;
-                const uint32_t nslots = (R.dim == 3) ? (uint32_t)R.L * (uint32_t)R.L : (uint32_t)R.L;
-                const int t = items[i].tile;
-                const uint32_t c0 = (uint32_t)(((uint64_t)t * nslots) / (uint32_t)R.ntiles);
-                const uint32_t c1 = (uint32_t)(((uint64_t)(t + 1) * nslots) / (uint32_t)R.ntiles);
-                if (threadIdx.x == 0) pflag_local = 0;
-                __syncthreads();
-                perc_chunk(R, c0, c1, &pflag_local);
-                __syncthreads();
-                if (threadIdx.x == 0 && pflag_local) atomicOr(R.pflag, 1);
-            }
-            if (!grid_barrier(ctl, timeout_ticks)) return;
-            for (int i = i0; i < i1; ++i) {
-                SwRep* Rp = &reps[items[i].rep];
-                uint32_t s;
-                if (items[i].tile != 0 || !(Rp->flags & FLAG_PCC) || !rep_runs(*Rp, it, n_sweeps, s)) continue;
-                if (threadIdx.x == 0) pcc_update(Rp, s);
-            }
-            if (!grid_barrier(ctl, timeout_ticks)) return;
-        }
-    }
-
-    // ---- E, M after the last sweep of every recording replica
-    if (any_series) {
-        int cur = -1;
-        int64_t e = 0, m = 0;
-        int64_t* dst = nullptr;
-        for (int i = i0; i <= i1; ++i) {
-            const int rep = (i < i1) ? items[i].rep : -2;
-            if (rep != cur) {
-                if (cur >= 0 && dst) {
-                    int64_t ee = e, mm = m;
-                    block_sum2(ee, mm, red);
-                    if (threadIdx.x == 0) {
-                        atomicAdd((unsigned long long*)&dst[0], (unsigned long long)ee);
-                        atomicAdd((unsigned long long*)&dst[1], (unsigned long long)mm);
-                    }
-                }
-                e = m = 0;
-                dst = nullptr;
-                cur = rep;
-                if (rep >= 0) {
-                    const SwRep& R = reps[rep];
-                    const uint64_t target = min((uint64_t)R.sweep + (uint64_t)n_sweeps, (uint64_t)R.limit);
-                    if (R.active && (R.flags & FLAG_SERIES) && target >= 1 && R.measured < target)
-                        dst = R.series + 2 * (size_t)(target - 1);
-                }
-            }
-            if (i == i1) break;
-            if (!dst) continue;
-            const SwRep R = reps[rep];
-            // the tile's share of the site range
-            const uint32_t a0 = (uint32_t)(((uint64_t)items[i].tile * R.N) / (uint32_t)R.ntiles);
-            const uint32_t a1 = (uint32_t)(((uint64_t)(items[i].tile + 1) * R.N) / (uint32_t)R.ntiles);
-            measure_range(R, a0 + threadIdx.x, a1, kBlock, e, m);
-        }
-    }
-    if (!grid_barrier(ctl, timeout_ticks)) return;
-
-    // ---- advance the counters (no workgroup reads them after the barriers above)
-    if (blockIdx.x == 0) {
-        const int nrep = ctl->nreps;
-        for (int r = threadIdx.x; r < nrep; r += kBlock) {
-            SwRep* Rp = &reps[r];
-            if (!Rp->active) continue;
-            const uint64_t target = min((uint64_t)Rp->sweep + (uint64_t)n_sweeps, (uint64_t)Rp->limit);
-            if (Rp->flags & FLAG_SERIES) Rp->measured = (uint32_t)max((uint64_t)Rp->measured, target);
-            Rp->sweep = (uint32_t)target;
-        }
+    block_sum2(e, m, red);
+    if (threadIdx.x == 0) {
+        atomicAdd((unsigned long long*)&dst[0], (unsigned long long)e);
+        atomicAdd((unsigned long long*)&dst[1], (unsigned long long)m);
     }
 }
 
+// K1 over the work list, with E, M of the incoming configuration summed per replica
+template <class C2, class C3>
+__global__ __launch_bounds__(kBlock) void kb1_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
+                                                     int n_sweeps)
+{
+    __shared__ __align__(16) char smem[cmax2(sizeof(K1Smem<C2>), sizeof(K1Smem<C3>))];
+    __shared__ int64_t red[2 * kBlock / 64];
+    int i0, i1;
+    chunk_of(nitems, i0, i1);
+    int cur = -1;
+    int64_t e = 0, m = 0;
+    int64_t* dst = nullptr;
+    for (int i = i0; i <= i1; ++i) {
+        const int rep = (i < i1) ? items[i].rep : -2;
+        if (rep != cur) {
+            if (cur >= 0 && dst) flush_em(e, m, dst, red);   // sums of the previous replica
+            e = m = 0;
+            dst = nullptr;
+            cur = rep;
+            if (rep >= 0) {
+                const SwRep& R = reps[rep];
+                uint32_t s;
+                if (rep_runs(R, it, n_sweeps, s) && (R.flags & FLAG_SERIES) && s >= 1 && (it > 0 || R.measured < R.sweep))
+                    dst = R.series + 2 * (size_t)(s - 1);
+            }
+        }
+        if (i == i1) break;
+        const SwRep& R = reps[rep];
+        uint32_t s;
+        if (!rep_runs(R, it, n_sweeps, s)) continue;
+        if (R.dim == 2)
+            k1_tile<C2>(R, items[i].tile, s, R.thr, *reinterpret_cast<K1Smem<C2>*>(smem), dst != nullptr, e, m);
+        else
+            k1_tile<C3>(R, items[i].tile, s, R.thr, *reinterpret_cast<K1Smem<C3>*>(smem), dst != nullptr, e, m);
+    }
+}
+
+template <class C2, class C3>
+__global__ __launch_bounds__(kBlock) void kb2_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
+                                                     int n_sweeps)
+{
+    int i0, i1;
+    chunk_of(nitems, i0, i1);
+    for (int i = i0; i < i1; ++i) {
+        const SwRep& R = reps[items[i].rep];
+        uint32_t s;
+        if (!rep_runs(R, it, n_sweeps, s)) continue;
+        if (R.dim == 2) k2_tile<C2>(R, items[i].tile, s);
+        else k2_tile<C3>(R, items[i].tile, s);
+    }
+}
+
+template <class C2, class C3>
+__global__ __launch_bounds__(kBlock) void kbc_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
+                                                     int n_sweeps)
+{
+    int i0, i1;
+    chunk_of(nitems, i0, i1);
+    for (int i = i0; i < i1; ++i) {
+        const SwRep& R = reps[items[i].rep];
+        uint32_t s;
+        if (!(R.flags & FLAG_PCC) || !rep_runs(R, it, n_sweeps, s)) continue;
+        if (R.dim == 2) k_cand_tile<C2>(R, items[i].tile, s);
+        else k_cand_tile<C3>(R, items[i].tile, s);
+    }
+}
+
+template <class C2, class C3>
+__global__ __launch_bounds__(kBlock) void kb3_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
+                                                     int n_sweeps)
+{
+    __shared__ __align__(16) char smem[cmax2(sizeof(K3Smem<C2>), sizeof(K3Smem<C3>))];
+    int i0, i1;
+    chunk_of(nitems, i0, i1);
+    for (int i = i0; i < i1; ++i) {
+        const SwRep& R = reps[items[i].rep];
+        uint32_t s;
+        if (!rep_runs(R, it, n_sweeps, s)) continue;
+        if (R.dim == 2) k3_tile<C2>(R, items[i].tile, s, *reinterpret_cast<K3Smem<C2>*>(smem));
+        else k3_tile<C3>(R, items[i].tile, s, *reinterpret_cast<K3Smem<C3>*>(smem));
+    }
+}
+
+// PCC coverage test: tile t of a replica checks its share of the candidate slots
+__global__ __launch_bounds__(kBlock) void kbp_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
+                                                     int n_sweeps)
+{
+    __shared__ int pflag_local;
+    int i0, i1;
+    chunk_of(nitems, i0, i1);
+    for (int i = i0; i < i1; ++i) {
+        const SwRep& R = reps[items[i].rep];
+        uint32_t s;
+        if (!(R.flags & FLAG_PCC) || !rep_runs(R, it, n_sweeps, s)) continue;
+        const uint32_t nslots = (R.dim == 3) ? (uint32_t)R.L * (uint32_t)R.L : (uint32_t)R.L;
+        const int t = items[i].tile;
+        const uint32_t c0 = (uint32_t)(((uint64_t)t * nslots) / (uint32_t)R.ntiles);
+        const uint32_t c1 = (uint32_t)(((uint64_t)(t + 1) * nslots) / (uint32_t)R.ntiles);
+        if (threadIdx.x == 0) pflag_local = 0;
+        __syncthreads();
+        perc_chunk(R, c0, c1, &pflag_local);
+        __syncthreads();
+        if (threadIdx.x == 0 && pflag_local) atomicOr(R.pflag, 1);
+    }
+}
+
+// PCC feedback: one thread per replica
+__global__ __launch_bounds__(kBlock) void kbu_kernel(SwRep* reps, int nreps, int it, int n_sweeps)
+{
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= nreps) return;
+    SwRep* Rp = &reps[r];
+    uint32_t s;
+    if (!(Rp->flags & FLAG_PCC) || !rep_runs(*Rp, it, n_sweeps, s)) return;
+    pcc_update(Rp, s);
+}
+
+// E, M after the last sweep of every recording replica
+__global__ __launch_bounds__(kBlock) void kbm_kernel(SwRep* reps, const EngineItem* items, int nitems, int n_sweeps)
+{
+    __shared__ int64_t red[2 * kBlock / 64];
+    int i0, i1;
+    chunk_of(nitems, i0, i1);
+    int cur = -1;
+    int64_t e = 0, m = 0;
+    int64_t* dst = nullptr;
+    for (int i = i0; i <= i1; ++i) {
+        const int rep = (i < i1) ? items[i].rep : -2;
+        if (rep != cur) {
+            if (cur >= 0 && dst) flush_em(e, m, dst, red);
+            e = m = 0;
+            dst = nullptr;
+            cur = rep;
+            if (rep >= 0) {
+                const SwRep& R = reps[rep];
+                const uint64_t target = min((uint64_t)R.sweep + (uint64_t)n_sweeps, (uint64_t)R.limit);
+                if (R.active && (R.flags & FLAG_SERIES) && target >= 1 && R.measured < target)
+                    dst = R.series + 2 * (size_t)(target - 1);
+            }
+        }
+        if (i == i1) break;
+        if (!dst) continue;
+        const SwRep& R = reps[rep];
+        // the tile's share of the site range
+        const uint32_t a0 = (uint32_t)(((uint64_t)items[i].tile * R.N) / (uint32_t)R.ntiles);
+        const uint32_t a1 = (uint32_t)(((uint64_t)(items[i].tile + 1) * R.N) / (uint32_t)R.ntiles);
+        measure_range(R, a0 + threadIdx.x, a1, kBlock, e, m);
+    }
+}
+
+// advance the sweep counters of the graph's n sweeps (last node)
+__global__ __launch_bounds__(kBlock) void kbfin_kernel(SwRep* reps, int nreps, int n_sweeps)
+{
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= nreps) return;
+    SwRep* Rp = &reps[r];
+    if (!Rp->active) return;
+    const uint64_t target = min((uint64_t)Rp->sweep + (uint64_t)n_sweeps, (uint64_t)Rp->limit);
+    if (Rp->flags & FLAG_SERIES) Rp->measured = (uint32_t)max((uint64_t)Rp->measured, target);
+    Rp->sweep = (uint32_t)target;
+}
 // ---------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------
@@ -550,18 +523,30 @@ int launch_set_state(SwRep* d, uint32_t sweep, uint32_t measured, double p, uint
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-int engine_grid_limit()
+int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, int nitems, int n_sweeps, int any_pcc,
+                 int any_series, int grid, hipStream_t stream)
 {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kengine_kernel, kBlock, 0) != hipSuccess) return -1;
-    return nb * device_cu_count();
-}
-
-int launch_engine(SwRep* reps, const EngineItem* items, int nitems, EngineCtl* ctl, int n_sweeps, int any_pcc,
-                  int any_series, int grid, uint64_t timeout_ticks, hipStream_t stream)
-{
-    hipLaunchKernelGGL(kengine_kernel, dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, ctl, n_sweeps,
-                       any_pcc, any_series, timeout_ticks);
+    const int rgrid = (nreps + kBlock - 1) / kBlock;
+    switch (variant) {
+#define SW_BATCH(i, C2, C3)                                                                                          \
+    case i:                                                                                                          \
+        for (int it = 0; it < n_sweeps; ++it) {                                                                      \
+            hipLaunchKernelGGL((kb1_kernel<C2, C3>), dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
+            hipLaunchKernelGGL((kb2_kernel<C2, C3>), dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
+            if (any_pcc)                                                                                             \
+                hipLaunchKernelGGL((kbc_kernel<C2, C3>), dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
+            hipLaunchKernelGGL((kb3_kernel<C2, C3>), dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
+            if (any_pcc) {                                                                                           \
+                hipLaunchKernelGGL(kbp_kernel, dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
+                hipLaunchKernelGGL(kbu_kernel, dim3(rgrid), dim3(kBlock), 0, stream, reps, nreps, it, n_sweeps);     \
+            }                                                                                                        \
+        }                                                                                                            \
+        break;
+        SW_ENGINE_PAIRS(SW_BATCH)
+        default: return -1;
+    }
+    if (any_series) hipLaunchKernelGGL(kbm_kernel, dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, n_sweeps);
+    hipLaunchKernelGGL(kbfin_kernel, dim3(rgrid), dim3(kBlock), 0, stream, reps, nreps, n_sweeps);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

@@ -3,8 +3,8 @@
 // A handle owns R replicas.  For each it keeps a host mirror of the device
 // descriptor (SwRep), the device buffers, and the bookkeeping of the sweep
 // counter and the (E_int, M) series.  Plain mode enqueues the phase kernels
-// replica by replica; batched mode replays a hipGraph holding one launch of
-// the persistent engine over every replica's tiles.
+// replica by replica; batched mode replays a hipGraph whose phase kernels
+// each run over the work list of every replica's tiles.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -277,6 +277,17 @@ int handle_sync(sw_lattice* h)
 {
     hipError_t e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (h->err) {
+        int32_t bits = 0;
+        e = hipMemcpy(&bits, h->err, sizeof(bits), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "reading the consistency-check word");
+        if (bits) {
+            const int32_t zero = 0;
+            (void)hipMemcpy(h->err, &zero, sizeof(zero), hipMemcpyHostToDevice);
+            return fail(SW_EHIP, "device consistency check failed (bits 0x%x): results of the last sweeps are invalid",
+                        (unsigned)bits);
+        }
+    }
     return SW_OK;
 }
 
@@ -285,18 +296,6 @@ int sync_mirror(sw_lattice* h)
 {
     int rc = handle_sync(h);
     if (rc) return rc;
-    if (h->ctl) {
-        EngineCtl c{};
-        hipError_t e = hipMemcpy(&c, h->ctl, sizeof(c), hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return hip_fail(e, "reading the engine state");
-        if (c.abort) {
-            EngineCtl z{};
-            z.nreps = (int)h->reps.size();
-            (void)hipMemcpy(h->ctl, &z, sizeof(z), hipMemcpyHostToDevice);
-            h->mirror_stale = true;
-            return fail(SW_EHIP, "persistent engine aborted: a grid barrier timed out (grid not co-resident)");
-        }
-    }
     if (!h->mirror_stale) return SW_OK;
     std::vector<SwRep> tmp(h->reps.size());
     hipError_t e = hipMemcpy(tmp.data(), h->d_reps, tmp.size() * sizeof(SwRep), hipMemcpyDeviceToHost);
@@ -501,6 +500,22 @@ static void drop_graph(sw_lattice* h)
     h->graph_n = -1;
 }
 
+// the batched kernels are compiled for pairs (2D shape i, 3D shape i): all
+// active replicas of a batched handle must use the same shape index
+int engine_variant(sw_lattice* h, int* variant)
+{
+    int v = -1;
+    for (auto& r : h->reps) {
+        if (!r.h.active) continue;
+        if (v < 0) v = r.h.shape;
+        else if (r.h.shape != v)
+            return fail(SW_ESTATE, "batched mode needs every replica on the same tile-shape index (%d and %d)", v,
+                        r.h.shape);
+    }
+    *variant = v < 0 ? 0 : v;
+    return SW_OK;
+}
+
 int batched_sweep(sw_lattice* h, int32_t n)
 {
     int rc = sync_mirror(h);
@@ -514,38 +529,29 @@ int batched_sweep(sw_lattice* h, int32_t n)
         any_pcc = any_pcc || (m.flags & FLAG_PCC);
         any_series = any_series || (m.flags & FLAG_SERIES);
     }
-    if (!h->ctl) {
-        rc = dmalloc((void**)&h->ctl, sizeof(EngineCtl), "engine control");
-        if (rc) return rc;
-        EngineCtl z{};
-        z.nreps = (int)h->reps.size();
-        hipError_t e = hipMemcpy(h->ctl, &z, sizeof(z), hipMemcpyHostToDevice);
-        if (e != hipSuccess) return hip_fail(e, "initialising the engine control block");
-    }
     if (h->items_dirty || !h->items) {
         rc = build_items(h);
         if (rc) return rc;
     }
     if (h->nitems == 0 || n == 0) return SW_OK;
-    if (h->engine_grid_limit <= 0) {
-        h->engine_grid_limit = engine_grid_limit();
-        if (h->engine_grid_limit <= 0) return fail(SW_EHIP, "occupancy query for the engine failed");
-    }
-    int grid = std::min(h->engine_grid_limit, h->engine_grid_cap > 0 ? h->engine_grid_cap : h->engine_grid_limit);
-    grid = std::min(grid, h->nitems);
+    int variant = 0;
+    rc = engine_variant(h, &variant);
+    if (rc) return rc;
+    int grid = std::min(device_cu_count() * h->batch_per_cu, h->nitems);
     if (grid >= 8) grid -= grid % 8;
     if (grid < 1) grid = 1;
-    const uint64_t timeout = device_wallclock_hz() * 2ull;
-    if (h->graph_n != n || h->graph_grid != grid || h->graph_flags != (int)(any_pcc * 2 + any_series)) {
+    if (h->graph_n != n || h->graph_grid != grid || h->graph_flags != (int)(any_pcc * 2 + any_series) ||
+        h->graph_variant != variant) {
         drop_graph(h);
         hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-        int lrc = launch_engine(h->d_reps, h->items, h->nitems, h->ctl, n, any_pcc, any_series, grid, timeout, h->stream);
+        int lrc = launch_batch(variant, h->d_reps, (int)h->reps.size(), h->items, h->nitems, n, any_pcc, any_series,
+                               grid, h->stream);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(h->stream, &g);
         if (lrc || e != hipSuccess || !g) {
             if (g) (void)hipGraphDestroy(g);
-            return fail(SW_EHIP, "capturing the engine launch failed");
+            return fail(SW_EHIP, "capturing the batched launches failed");
         }
         h->graph = g;
         e = hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0);
@@ -556,6 +562,7 @@ int batched_sweep(sw_lattice* h, int32_t n)
         h->graph_n = n;
         h->graph_grid = grid;
         h->graph_flags = (int)(any_pcc * 2 + any_series);
+        h->graph_variant = variant;
     }
     hipEvent_t ev;
     timing_begin(h, 5, &ev);
@@ -627,9 +634,15 @@ int sw_init(const sw_params* params, int32_t n_replicas, int32_t device, void* h
     int rc = SW_OK;
     for (int32_t r = 0; r < n_replicas && !rc; ++r) rc = replica_alloc(h->reps[r], &params[r], default_shape(params[r].dim), h->stream);
     if (!rc) rc = dmalloc((void**)&h->d_reps, sizeof(SwRep) * (size_t)n_replicas, "replica descriptors");
+    if (!rc) rc = dmalloc((void**)&h->err, sizeof(int32_t), "consistency-check word");
+    if (!rc && hipMemsetAsync(h->err, 0, sizeof(int32_t), h->stream) != hipSuccess)
+        rc = fail(SW_EHIP, "clearing the consistency-check word");
     if (!rc) {
         std::vector<SwRep> tmp(n_replicas);
-        for (int32_t r = 0; r < n_replicas; ++r) tmp[r] = h->reps[r].h;
+        for (int32_t r = 0; r < n_replicas; ++r) {
+            h->reps[r].h.err = h->err;
+            tmp[r] = h->reps[r].h;
+        }
         e = hipMemcpyAsync(h->d_reps, tmp.data(), tmp.size() * sizeof(SwRep), hipMemcpyHostToDevice, h->stream);
         if (e != hipSuccess) rc = hip_fail(e, "uploading replica descriptors");
         if (!rc) e = hipStreamSynchronize(h->stream);
@@ -915,7 +928,7 @@ int sw_free(sw_lattice* h)
     for (auto& r : h->reps) replica_free(r);
     dfree(h->d_reps);
     dfree(h->items);
-    dfree(h->ctl);
+    dfree(h->err);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
     return SW_OK;

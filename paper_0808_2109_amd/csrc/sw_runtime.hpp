@@ -45,6 +45,7 @@ struct sw_lattice {
     int per_cu[3] = {8, 8, 8};          // plain-kernel workgroups per CU (K1, K2, K3)
     std::vector<sw::ReplicaH> reps;
     sw::SwRep* d_reps = nullptr;        // device descriptor array
+    int32_t* err = nullptr;             // device consistency-check word shared by the replicas
     bool mirror_stale = false;          // device-side counters changed since the last read
     // timing
     bool timing = false;
@@ -52,19 +53,18 @@ struct sw_lattice {
     std::vector<hipEvent_t> event_pool;
     double ms[6] = {0, 0, 0, 0, 0, 0};
     int64_t launches[6] = {0, 0, 0, 0, 0, 0};
-    // persistent engine
+    // batched execution (work list of all replicas' tiles, replayed graph)
     sw::EngineItem* items = nullptr;
     size_t items_cap = 0;
     int nitems = 0;
     bool items_dirty = true;
-    sw::EngineCtl* ctl = nullptr;
-    int engine_grid_limit = 0;
-    int engine_grid_cap = 0;            // 0: occupancy limit
+    int batch_per_cu = 8;               // workgroups per CU of the batched launches
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int graph_n = -1;
     int graph_grid = -1;
     int graph_flags = -1;
+    int graph_variant = -1;
 };
 
 namespace sw {
@@ -74,5 +74,6 @@ int push_desc(sw_lattice* h, int r);
 int ensure_capacity(sw_lattice* h, int r, uint64_t need);
 int plain_sweep(sw_lattice* h, int r, int32_t n);
 int batched_sweep(sw_lattice* h, int32_t n);
+int engine_variant(sw_lattice* h, int* variant);
 int timing_collect(sw_lattice* h);
 }  // namespace sw

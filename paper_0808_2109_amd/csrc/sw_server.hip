@@ -4,9 +4,9 @@
 // submit.  Each tick the server
 //   1. admits queued jobs in arrival order while a slot is free and the
 //      resident footprint stays within the memory budget,
-//   2. runs up to `sweeps_per_tick` sweeps of every resident job in one
-//      launch of the persistent engine (replayed from a hipGraph while the
-//      resident set is unchanged), each job stopping at its own sweep count,
+//   2. runs up to `sweeps_per_tick` sweeps of every resident job as one
+//      batched hipGraph launch (replayed while the resident set is
+//      unchanged), each job stopping at its own sweep count,
 //   3. retires finished jobs: records (E_int, M), the FNV-1a hash of the final
 //      spins and the time stamps, and frees the slot.
 // A job's random stream is keyed by its own seed and sweep index, never by
@@ -103,6 +103,7 @@ static int admit(sw_server* s)
         if (rc) return rc;
         r.h.limit = (uint32_t)j.n_sweeps;
         r.h.active = 1;
+        r.h.err = s->lat->err;
         r.labels_valid = false;
         rc = push_desc(s->lat, slot);
         if (rc) return rc;
