@@ -14,7 +14,7 @@ Extra objects on the JSON line:
                 the rocprofv3 FETCH_SIZE / WRITE_SIZE summary in profiles/ when
                 it was taken on the current kernel sources, else null
   cpu_baseline  the CPU oracle (single thread) on a bounded sample
-  batched       (--batched) 512 uneven replicas: persistent engine in a hipGraph
+  batched       (--batched) 512 uneven replicas: batched phase launches replayed from a hipGraph
                 vs plain per-lattice launches, site-updates/s each
 
 Usage: python bench.py [--gpus 1] [--steps 200] [--warmup 5] [--no-cpu-baseline]
@@ -34,13 +34,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SW site-updates/sec (batched vs plain) + % HBM roofline; p50/p99 job latency"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per site of each kernel (see the kernel notes in the design doc)
+# algorithmic HBM bytes per site of each kernel: what the kernel must move,
+# whatever it actually fetches
 ALGO_BYTES_PER_SITE = {
     "k1_bond_label": 3.0,     # read the int8 spin, write the 16-bit tile label
     "k3_flip": 3.0,           # read the 16-bit tile label, write the int8 spin
-    "k2_merge_fliptab": 0.125,  # write the per-sweep flip-bit table (1 bit per site)
+    "k3_resolve": 0.25,       # read the border bitmap, write the border flip bits (1 bit each per site)
 }
-KERNEL_SYMBOLS = {"k1_bond_label": "k1_kernel", "k2_merge_fliptab": "k2_kernel", "k3_flip": "k3_kernel"}
+KERNEL_SYMBOLS = {"k1_bond_label": "k1_kernel", "k2_merge": "k2_kernel", "k3_flip": "k3_kernel",
+                  "k3_resolve": "k3a_kernel"}
 SOURCES = ["paper_0808_2109_amd/csrc/sw_device.hpp", "paper_0808_2109_amd/csrc/sw_kernels.hip"]
 
 

@@ -6,18 +6,18 @@
 //   K1  per tile: load the spins (+ the far halo) as one bit mask per row,
 //       draw the bonds of the tile's own links from Philox as bit masks, label
 //       the tile's clusters in LDS (runs along x from the bond masks, a
-//       union-find over the remaining links), write a 16-bit tile-local label
-//       per site and the bits of the tile's open links that leave it.  The
+//       union-find over the runs of neighbouring rows), write a 16-bit
+//       tile-local label per site, the labels of the tile's face sites, the
+//       bits of the tile's open links that leave it and its border roots.  The
 //       tile plays the part of a domain of Sec. II.
-//   K2  per tile: join, in a global union-find over tile-local roots, the two
-//       ends of every open link that leaves the tile (the border
+//   K2  per far-face site: join, in a global union-find over tile-local roots,
+//       the two ends of every open link that leaves a tile (the border
 //       reconciliation of Sec. II, in one pass instead of the master's second
-//       labelling or the iterated neighbour exchange), and write this sweep's
-//       flip-bit table.
-//   K3  per tile: resolve every tile-local root once to its cluster root (the
-//       smallest site index of the cluster: the label identity that the
-//       min-label rule of Sec. II.B converges to) and give every site its
-//       cluster's new spin (Sec. I step 3).
+//       labelling or the iterated neighbour exchange).
+//   K3a per border root: find its cluster root (the smallest site index of the
+//       cluster: the label identity that the min-label rule of Sec. II.B
+//       converges to) and that cluster's flip bit.
+//   K3b per tile: give every site its cluster's new spin (Sec. I step 3).
 // plus the extension-rule percolation test and p feedback of Sec. III.
 //
 // Every union hooks the larger root under the smaller one, so the final roots
@@ -46,6 +46,8 @@ struct SwRep {
     int32_t tx, ty, tz;         // tile extents
     int32_t ntx, nty, ntz, ntiles;
     int32_t xwords;             // crossing-bit words per tile
+    int32_t fbw;                // words of a per-tile site bitmap (TS / 32)
+    int32_t ft;                 // face sites per face set of a tile (F0 + F1 + F2)
     uint32_t flags;
     uint64_t seed;
     uint64_t thr;               // threshold of the next sweep (<= 2^32)
@@ -64,7 +66,9 @@ struct SwRep {
     int32_t* par;               // N global union-find parents (border roots only)
     int32_t* lab32;             // N final labels (FLAG_KEEP or FLAG_PCC), else null
     uint32_t* xbits;            // ntiles * xwords crossing-link bits
-    uint32_t* fliptab;          // 4 * ceil(N/128) words: this sweep's flip bits
+    uint32_t* fbits;            // ntiles * fbw: border roots of each tile (bit per tile-local site)
+    uint32_t* bflip;            // ntiles * fbw: flip bits of those border roots
+    uint16_t* face;             // ntiles * 2 * ft: labels of the near, then the far face sites
     int64_t* series;            // 2 * series_cap
     int64_t* acc;               // 2 scratch accumulators (measure)
     uint64_t* cand;             // PCC: dim * N candidate marks (tag << 32 | ~slot)
@@ -134,6 +138,8 @@ struct TileCfg {
     static constexpr int F0 = TY * TZ, F1 = TX * TZ, F2 = (D == 3) ? TX * TY : 0;
     static constexpr int W0 = (F0 + 31) / 32, W1 = (F1 + 31) / 32, W2 = (F2 + 31) / 32;
     static constexpr int XW = W0 + W1 + W2;
+    static constexpr int FT = F0 + F1 + F2;   // face sites per face set (x, y, z faces in turn)
+    static constexpr int FBW = TS / 32;       // words of a bitmap over the tile's sites
     static constexpr int NB = TX / 16;        // Philox bond blocks per aligned row
     static_assert(TX == 32 || TX == 64, "a wave64 covers whole tile rows");
     static_assert(TS % kBlock == 0, "whole sites per thread");
@@ -250,6 +256,35 @@ __device__ __forceinline__ void lds_unite(int* par, int a, int b)
     }
 }
 
+// Union of the sets of a and b for the tile labelling: both chains are walked
+// together (one LDS round trip per step), the larger root is hooked under the
+// smaller with an atomic min (from the displaced parent again when another
+// thread hooked it first), and a and b then point straight at the joint root,
+// which is an ancestor of both, so the store keeps every set intact.
+__device__ __forceinline__ void lds_join(int* par, int a, int b)
+{
+    const int a0 = a, b0 = b;
+    int lo;
+    while (true) {
+        while (true) {
+            const int pa = lds_load(&par[a]);
+            const int pb = lds_load(&par[b]);
+            if (pa == a && pb == b) break;
+            a = pa;
+            b = pb;
+        }
+        lo = min(a, b);
+        if (a == b) break;
+        const int hi = max(a, b);
+        const int old = atomicMin(&par[hi], lo);
+        if (old == hi) break;
+        a = old;
+        b = lo;
+    }
+    if (a0 != lo) lds_store(&par[a0], lo);
+    if (b0 != lo) lds_store(&par[b0], lo);
+}
+
 __device__ __forceinline__ int g_load(const int* p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -316,342 +351,534 @@ __device__ __forceinline__ uint32_t ro_find(const SwRep& R, uint32_t x)
 }
 
 // --------------------------------------------------------------------------
-// K1: bonds + tile labelling.
+// Bit tools.
 // --------------------------------------------------------------------------
-template <class C>
-struct K1Smem {
-    int32_t par[C::TS];
-    uint64_t S[C::NRH];        // spin-up bit masks of the rows (bit x), incl. the +y / +z halo rows
-    uint64_t OPN[C::D][C::NR]; // open-bond masks of the tile's own links, per direction and row
-    uint64_t RR[C::NR];        // x-runs: open x-bonds that stay inside the tile
-    uint8_t HB[C::NRH];        // spin-up bit of the +x halo site of each row
-    uint8_t flag[C::TS];
-};
-
-// equal-spin masks of a row's own links in direction d (bit x: link (x, d))
-template <class C>
-__device__ __forceinline__ uint64_t eq_mask(const K1Smem<C>& sm, int ly, int lz, int d, int wx)
+// Per-byte unsigned compares of x against the byte y (y4 = y * 0x01010101):
+// the top bit of each byte of the result holds that byte's answer.  No borrow
+// or carry crosses a byte boundary: (x | 0x80) - (y & 0x7F) >= 1 per byte.
+__device__ __forceinline__ uint32_t bytes_lt(uint32_t x, uint32_t y4)
 {
-    const int hr = ly + (C::TY + 1) * lz;
-    const uint64_t s = sm.S[hr];
-    uint64_t nb;
-    if (d == 0) nb = (s >> 1) | ((uint64_t)sm.HB[hr] << (wx - 1));
-    else if (d == 1) nb = sm.S[hr + 1];
-    else nb = sm.S[hr + C::TY + 1];
-    return ~(s ^ nb) & low_bits(wx);
+    const uint32_t d = (x | 0x80808080u) - (y4 & 0x7F7F7F7Fu);
+    return ((~x & y4) | (~(x ^ y4) & ~d)) & 0x80808080u;
 }
 
+__device__ __forceinline__ uint32_t bytes_eq(uint32_t x, uint32_t y4)
+{
+    const uint32_t z = x ^ y4;
+    return ~(((z & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | z) & 0x80808080u;
+}
+
+// top bits of the four bytes (bits 7, 15, 23, 31) -> bits 0..3
+__device__ __forceinline__ uint32_t byte_msbs(uint32_t m) { return (((m >> 7) * 0x00204081u) >> 21) & 0xFu; }
+
+__device__ __forceinline__ uint32_t nibbles4(uint32_t a, uint32_t b, uint32_t c, uint32_t d)
+{
+    return byte_msbs(a) | (byte_msbs(b) << 4) | (byte_msbs(c) << 8) | (byte_msbs(d) << 12);
+}
+
+// highest set bit of s at or below x (s has bit 0 set)
+__device__ __forceinline__ int start_at(uint64_t s, int x)
+{
+    return 63 - __clzll((long long)(s & low_bits(x + 1)));
+}
+
+// number of set bits of `mask` below this lane
+__device__ __forceinline__ int lanes_below(uint64_t mask)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// LDS writes of this wave become visible to its other lanes (a wave's LDS
+// operations complete in order; this keeps the compiler from reordering)
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// flip bit of the cluster whose canonical label is c in sweep s
+__device__ __forceinline__ uint32_t flip_bit(uint32_t c, uint32_t s, uint32_t k0, uint32_t k1)
+{
+    const U4 q = philox10(c >> 7, 0u, s, kTagFlip, k0, k1);
+    return (pick(q, (c >> 5) & 3u) >> (c & 31u)) & 1u;
+}
+
+// flip bits of the wx sites gb .. gb+wx-1 (bit x <- site gb + x)
+__device__ __forceinline__ uint64_t row_flips(uint32_t gb, int wx, uint32_t s, uint32_t k0, uint32_t k1)
+{
+    uint64_t m = 0;
+    const uint32_t w0 = gb >> 5, w1 = (gb + (uint32_t)wx - 1u) >> 5;
+    uint32_t cur = 0xFFFFFFFFu;
+    U4 q{0u, 0u, 0u, 0u};
+    for (uint32_t w = w0; w <= w1; ++w) {
+        if ((w >> 2) != cur) {
+            cur = w >> 2;
+            q = philox10(cur, 0u, s, kTagFlip, k0, k1);
+        }
+        const uint64_t word = pick(q, w & 3u);
+        const int sh = (int)(w * 32u - gb);        // in [-31, 63]
+        m |= (sh >= 0) ? (word << sh) : (word >> (-sh));
+    }
+    return m & low_bits(wx);
+}
+
+// --------------------------------------------------------------------------
+// K1: bonds + tile labelling.  A tile has 64 rows (TY * TZ); each row is
+// split into parts of 16 sites, one thread per part (RQ = TX / 16 threads
+// per row, NT = 64 * RQ threads per tile, the RQ threads of a row adjacent in
+// one wave).
+//
+// A row is a set of bit masks over x, which every thread of the row holds
+// whole: S (spin up), OPN[d] (open bond of the link (x, d)) and SS (run
+// starts).  A run is a maximal stretch of a row joined by x-bonds; its node in
+// the union-find is its first site.  Unions only join runs of neighbouring
+// rows: for each pair of rows (y or z neighbours) one union per pair of
+// overlapping runs that share an open bond, made by the thread whose part
+// holds the first such bond.
+// --------------------------------------------------------------------------
+template <class C>
+struct K1Cfg {
+    static constexpr int RQ = C::TX / 16;      // threads per row
+    static constexpr int NT = C::NR * RQ;      // threads per tile
+    static_assert(C::NR == 64, "64 rows per tile");
+};
+
+template <class C>
+struct alignas(16) K1Smem {
+    int32_t par[C::TS];    // parents of the run starts (tile-local site indices)
+    uint32_t FB[C::FBW];   // border flag of every tile-local root
+    uint64_t S[C::NR];     // spin-up masks of the rows
+    uint64_t SS[C::NR];    // run starts of the rows
+    uint32_t XF[2];        // open links leaving through the far x face (bit = row)
+};
+
+// spins of 4 / 16 sites -> their up bits (a spin is up when it is positive)
+__device__ __forceinline__ uint32_t up4(uint32_t w)
+{
+    const uint32_t nz = (((w & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | w) & 0x80808080u;   // byte != 0
+    return byte_msbs(nz & ~w);
+}
+
+__device__ __forceinline__ uint32_t up16(uint4 v)
+{
+    return up4(v.x) | (up4(v.y) << 4) | (up4(v.z) << 8) | (up4(v.w) << 12);
+}
+
+// up bits of the n <= 16 sites p[0 .. n-1]; `wide` when p is 16-byte aligned and n = 16
+__device__ __forceinline__ uint32_t load_part(const int8_t* p, int n, bool wide)
+{
+    if (wide) return up16(*reinterpret_cast<const uint4*>(p));
+    uint32_t m = 0;
+    for (int x = 0; x < n; ++x) m |= (uint32_t)(p[x] > 0) << x;
+    return m;
+}
+
+// bit masks of a row's RQ parts (16 bits at 16q) -> the whole row, in every
+// thread of the row
+template <int RQ>
+__device__ __forceinline__ uint64_t row_gather(uint32_t part, int q)
+{
+    uint64_t v = (uint64_t)part << (16 * q);
+    if (RQ >= 2) v |= __shfl_xor(v, 1, 64);
+    if (RQ >= 4) v |= __shfl_xor(v, 2, 64);
+    return v;
+}
+
+// open bonds among the n <= 16 links lbase + x whose ends are equal (eq):
+// byte a of Philox(l >> 4, 0, s, BOND) for link l is the high byte of u; a tie
+// with thr >> 24 draws the low 24 bits.  `aligned` when lbase is a multiple
+// of 16 and n = 16: then one block holds all of them.
+__device__ inline uint32_t part_bonds(uint32_t eq, uint32_t lbase, int n, bool aligned, uint32_t s, uint32_t t_hi,
+                               uint32_t t_lo, uint32_t k0, uint32_t k1)
+{
+    if (!eq) return 0;
+    if (t_hi >= 256u) return eq;                     // P = 1: every equal link is a bond
+    if (aligned) {
+        const uint32_t y4 = t_hi * 0x01010101u;
+        const uint32_t blk = lbase >> 4;
+        const U4 q = philox10(blk, 0u, s, kTagBond, k0, k1);
+        uint32_t bits = nibbles4(bytes_lt(q.x, y4), bytes_lt(q.y, y4), bytes_lt(q.z, y4), bytes_lt(q.w, y4)) & eq;
+        uint32_t ties = nibbles4(bytes_eq(q.x, y4), bytes_eq(q.y, y4), bytes_eq(q.z, y4), bytes_eq(q.w, y4)) & eq;
+        while (ties) {
+            const int k = __ffs(ties) - 1;
+            ties &= ties - 1u;
+            const uint32_t l = blk * 16u + (uint32_t)k;
+            const U4 q2 = philox10(l >> 2, 0u, s, kTagRefine, k0, k1);
+            if ((pick(q2, l & 3u) & 0xFFFFFFu) < t_lo) bits |= 1u << k;
+        }
+        return bits;
+    }
+    uint32_t op = 0;
+    const uint32_t b0 = lbase >> 4, b1 = (lbase + (uint32_t)n - 1u) >> 4;
+    for (uint32_t blk = b0; blk <= b1; ++blk) {
+        const U4 q = philox10(blk, 0u, s, kTagBond, k0, k1);
+        for (int k = 0; k < 16; ++k) {
+            const int xl = (int)(blk * 16u + (uint32_t)k - lbase);
+            if (xl < 0 || xl >= n || !((eq >> xl) & 1u)) continue;
+            const uint32_t a = (pick(q, (uint32_t)k >> 2) >> (8 * (k & 3))) & 0xFFu;
+            bool open = a < t_hi;
+            if (a == t_hi) {
+                const uint32_t l = blk * 16u + (uint32_t)k;
+                const U4 q2 = philox10(l >> 2, 0u, s, kTagRefine, k0, k1);
+                open = (pick(q2, l & 3u) & 0xFFFFFFu) < t_lo;
+            }
+            if (open) op |= 1u << xl;
+        }
+    }
+    return op;
+}
+
+// Threads beyond K1Cfg<C>::NT (a workgroup sized for a larger tile) take part
+// in the barriers only.
 template <class C>
 __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<C>& sm, bool measure,
                         int64_t& e_acc, int64_t& m_acc)
 {
+    using K = K1Cfg<C>;
+    constexpr int RQ = K::RQ;
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const bool active = tid < K::NT;
+    const int r = active ? tid / RQ : 0, q = tid % RQ;
+    const int ly = r % C::TY, lz = r / C::TY;
     const TileGeo g = tile_geo<C>(R, t);
-    const int L = R.L;
+    const uint32_t L = (uint32_t)R.L;
     const uint32_t N = R.N;
     const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
+    const bool rowok = active && ly < g.wy && lz < g.wz;
+    const int xp = 16 * q;                                  // first site of this thread's part
+    const int np = max(0, min(16, g.wx - xp));              // sites of the part inside the tile
+    const bool partok = rowok && np > 0;
+    const uint64_t lbw = low_bits(g.wx);
+    const bool wide = (L & 15u) == 0;                       // rows and parts start on 16-site boundaries
+    const uint32_t yy = (uint32_t)(g.y0 + ly), zz = (uint32_t)(g.z0 + lz);
+    const uint32_t gi0 = (uint32_t)g.x0 + L * (yy + L * zz);   // first site of the row
+    const bool edgeY = ly == g.wy - 1, edgeZ = C::D == 3 && lz == g.wz - 1;
 
-    // 1) spins as bit masks: rows of the tile, the +y halo row(s), the +z halo
-    //    plane, and the +x halo site of every row
-    {
-        int8_t v[C::LOADIT];
-        const int x = lane % C::TX;
-        int hb = 0;
-        if (tid < C::NR) {
-            const int ly = tid % C::TY, lz = tid / C::TY;
-            if (ly < g.wy && lz < g.wz) {
-                const int gx = (g.x0 + g.wx == L) ? 0 : g.x0 + g.wx;
-                hb = R.spins[(uint32_t)gx + (uint32_t)L * ((uint32_t)(g.y0 + ly) + (uint32_t)L * (uint32_t)(g.z0 + lz))] > 0;
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < C::LOADIT; ++i) {
-            const int hr = (wave + 4 * i) * C::RPW + lane / C::TX;
-            const int hy = hr % (C::TY + 1), hz = hr / (C::TY + 1);
-            bool need = hr < C::NRH && x < g.wx && hy <= g.wy;
-            if (C::D == 3) need = need && hz <= g.wz && !(hy == g.wy && hz == g.wz);
-            v[i] = 0;
-            if (need) {
-                int gy = g.y0 + hy, gz = g.z0 + hz;
-                if (gy == L) gy = 0;
-                if (C::D == 3 && gz == L) gz = 0;
-                v[i] = R.spins[(uint32_t)(g.x0 + x) + (uint32_t)L * ((uint32_t)gy + (uint32_t)L * (uint32_t)gz)];
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < C::LOADIT; ++i) {
-            const int hr = (wave + 4 * i) * C::RPW + lane / C::TX;
-            const uint64_t b = __ballot(v[i] > 0);
-            if (x == 0 && hr < C::NRH) sm.S[hr] = (b >> (lane - x)) & low_bits(C::TX);
-        }
-        if (tid < C::NR) {
-            const int ly = tid % C::TY, lz = tid / C::TY;
-            sm.HB[ly + (C::TY + 1) * lz] = (uint8_t)hb;
-#pragma unroll
-            for (int d = 0; d < C::D; ++d) sm.OPN[d][tid] = 0;
-        }
-        for (int k = tid; k < C::TS; k += kBlock) sm.flag[k] = 0;
+    // 1) spins: the row, the +x halo site, and for the last row in y / z of
+    //    the tile the neighbour row beyond it
+    uint32_t mine = partok ? load_part(R.spins + gi0 + (uint32_t)xp, np, wide) : 0u;
+    const uint64_t S = row_gather<RQ>(mine, q);
+    uint32_t hb = 0;
+    if (rowok && q == RQ - 1) {
+        const uint32_t hx = ((uint32_t)(g.x0 + g.wx) == L) ? 0u : (uint32_t)(g.x0 + g.wx);
+        hb = R.spins[hx + L * (yy + L * zz)] > 0;
     }
+    const uint64_t HB = __shfl(hb, (threadIdx.x & 63) | (RQ - 1), 64);
+    uint32_t ypart = 0, zpart = 0;
+    if (partok && edgeY) {
+        const uint32_t ny = (yy + 1u == L) ? 0u : yy + 1u;
+        ypart = load_part(R.spins + (uint32_t)g.x0 + L * (ny + L * zz) + (uint32_t)xp, np, wide);
+    }
+    if (C::D == 3 && partok && edgeZ) {
+        const uint32_t nz = (zz + 1u == L) ? 0u : zz + 1u;
+        zpart = load_part(R.spins + (uint32_t)g.x0 + L * (yy + L * nz) + (uint32_t)xp, np, wide);
+    }
+    const uint64_t HY = row_gather<RQ>(ypart, q);
+    const uint64_t HZ = (C::D == 3) ? row_gather<RQ>(zpart, q) : 0ull;
+    if (active && q == 0) sm.S[r] = S;
+    if (tid < 2) sm.XF[tid] = 0;
+    for (int w = tid; w < C::FBW; w += blockDim.x) sm.FB[w] = 0;
+    for (int k = tid; k < C::TS; k += blockDim.x) sm.par[k] = k;
     __syncthreads();
 
-    // 2) bonds of the tile's own links (i, d), d < D: Philox blocks of 16 links
-    //    give the high byte a of u; ties with thr>>24 draw the low 24 bits
+    // 2) bonds of the row's own links (x, d), each thread those of its part
+    uint64_t opn[3] = {0, 0, 0};
     {
+        uint64_t eq[3] = {0, 0, 0};
+        if (rowok) {
+            eq[0] = ~(S ^ ((S >> 1) | (HB << (g.wx - 1)))) & lbw;
+            const uint64_t nbY = edgeY ? HY : sm.S[min(r + 1, C::NR - 1)];
+            eq[1] = ~(S ^ nbY) & lbw;
+            if (C::D == 3) {
+                const uint64_t nbZ = edgeZ ? HZ : sm.S[min(r + C::TY, C::NR - 1)];
+                eq[2] = ~(S ^ nbZ) & lbw;
+            }
+        }
         const uint32_t t_hi = (uint32_t)(thr >> 24);
         const uint32_t t_lo = (uint32_t)(thr & 0xFFFFFFu);
-        const int nslot = (L % 16 == 0) ? C::NB : C::NB + 1;
-        const int nitems = C::D * C::NR * nslot;
-        for (int it = tid; it < nitems; it += kBlock) {
-            const int j = it % nslot;
-            const int r = (it / nslot) % C::NR;
-            const int d = it / (nslot * C::NR);
-            const int ly = r % C::TY, lz = r / C::TY;
-            if (ly >= g.wy || lz >= g.wz) continue;
-            const uint32_t rowbase = (uint32_t)d * N + (uint32_t)g.x0 +
-                                     (uint32_t)L * ((uint32_t)(g.y0 + ly) + (uint32_t)L * (uint32_t)(g.z0 + lz));
-            const uint32_t blk = (rowbase >> 4) + (uint32_t)j;
-            if (blk * 16u >= rowbase + (uint32_t)g.wx) continue;
-            const uint64_t eq = eq_mask<C>(sm, ly, lz, d, g.wx);
-            const U4 q = philox10(blk, 0u, s, kTagBond, k0, k1);
-            uint64_t op = 0;
-            uint32_t ties = 0;
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const int x = (int)(blk * 16u + (uint32_t)k - rowbase);
-                if (x < 0 || x >= g.wx) continue;
-                if (!((eq >> x) & 1ull)) continue;
-                const uint32_t word = (k < 4) ? q.x : (k < 8) ? q.y : (k < 12) ? q.z : q.w;
-                const uint32_t a = (word >> (8 * (k & 3))) & 0xFFu;
-                if (a < t_hi) op |= 1ull << x;
-                if (a == t_hi) ties |= 1u << k;
-            }
-            while (ties) {
-                const int k = __ffs(ties) - 1;
-                ties &= ties - 1u;
-                const uint32_t l = blk * 16u + (uint32_t)k;
-                const U4 q2 = philox10(l >> 2, 0u, s, kTagRefine, k0, k1);
-                if ((pick(q2, l & 3u) & 0xFFFFFFu) < t_lo) op |= 1ull << (int)(l - rowbase);
-            }
-            if (op) atomicOr((unsigned long long*)&sm.OPN[d][r], (unsigned long long)op);
+        for (int d = 0; d < C::D; ++d) {
+            const uint32_t bits = partok ? part_bonds((uint32_t)(eq[d] >> xp) & 0xFFFFu, (uint32_t)d * N + gi0 + (uint32_t)xp,
+                                                      np, wide, s, t_hi, t_lo, k0, k1)
+                                         : 0u;
+            opn[d] = row_gather<RQ>(bits, q);
+        }
+        if (measure && partok) {
+            const uint64_t pm = low_bits(np) << xp;
+            m_acc += 2 * (int)__popcll(S & pm) - np;         // __popcll is unsigned
+#pragma unroll
+            for (int d = 0; d < C::D; ++d) e_acc += 2 * (int)__popcll(eq[d] & pm) - np;
         }
     }
-    __syncthreads();
-
-    // 3) outgoing open links (far faces) -> crossing bits; x-runs -> first
-    //    parents; E and M of the incoming configuration
+    // the x-bond of x = wx-1 leaves the tile: shifted out by the mask
+    const uint64_t SS = rowok ? (~(opn[0] << 1) & lbw) : 0ull;
+    if (active && q == 0) {
+        sm.SS[r] = SS;
+        if (rowok && ((opn[0] >> (g.wx - 1)) & 1ull)) atomicOr(&sm.XF[r >> 5], 1u << (r & 31));
+    }
+    // crossing bits of the far y / z faces (y: bit x + TX*lz, z: x + TX*ly);
+    // rows past the tile's extent write zeros
     {
         uint32_t* xb = R.xbits + (size_t)t * C::XW;
-        for (int w = tid; w < C::XW; w += kBlock) {
-            uint32_t bits = 0;
-            if (w < C::W0) {                       // face x = wx-1: bit ly + TY*lz
-                for (int b = 0; b < 32; ++b) {
-                    const int fb = w * 32 + b;
-                    if (fb >= C::F0) break;
-                    const int ly = fb % C::TY, lz = fb / C::TY;
-                    if (ly < g.wy && lz < g.wz) bits |= (uint32_t)((sm.OPN[0][fb] >> (g.wx - 1)) & 1ull) << b;
-                }
-            } else if (w < C::W0 + C::W1) {        // face y = wy-1: bit x + TX*lz
-                const int fb0 = (w - C::W0) * 32;
-                const int lz = fb0 / C::TX, x0 = fb0 % C::TX;
-                if (lz < g.wz) bits = (uint32_t)(sm.OPN[1][(g.wy - 1) + C::TY * lz] >> x0);
-            } else {                               // face z = wz-1: bit x + TX*ly
-                const int fb0 = (w - C::W0 - C::W1) * 32;
-                const int ly = fb0 / C::TX, x0 = fb0 % C::TX;
-                if (ly < g.wy) bits = (uint32_t)(sm.OPN[C::D - 1][ly + C::TY * (g.wz - 1)] >> x0);
-            }
-            xb[w] = bits;
-        }
-        const uint64_t inside = low_bits(g.wx - 1);   // x-bonds whose both ends are in the tile
-#pragma unroll 4
-        for (int i = 0; i < C::SITEIT; ++i) {
-            const int k = tid + kBlock * i;
-            const int x = k % C::TX, r = k / C::TX;
-            const int ly = r % C::TY, lz = r / C::TY;
-            int p = k;
-            if (x < g.wx && ly < g.wy && lz < g.wz) {
-                const uint64_t run = sm.OPN[0][r] & inside;
-                const uint64_t m = ~run & low_bits(x);            // closed x-bonds left of x
-                const int start = m ? 64 - __clzll((long long)m) : 0;
-                p = k - x + start;
-                if (x == 0) sm.RR[r] = run;
-            } else if (x == 0) {
-                sm.RR[r] = 0;
-            }
-            sm.par[k] = p;
-        }
-        if (measure) {
-            int e = 0, m = 0;
-            for (int r = tid; r < C::NR; r += kBlock) {
-                const int ly = r % C::TY, lz = r / C::TY;
-                if (ly >= g.wy || lz >= g.wz) continue;
-                const int hr = ly + (C::TY + 1) * lz;
-                m += 2 * __popcll(sm.S[hr]) - g.wx;
+        if (active && edgeY && (xp & 31) == 0)
+            xb[C::W0 + (C::TX * lz + xp) / 32] = rowok ? (uint32_t)(opn[1] >> xp) : 0u;
+        if (C::D == 3 && active && edgeZ && (xp & 31) == 0)
+            xb[C::W0 + C::W1 + (C::TX * ly + xp) / 32] = rowok ? (uint32_t)(opn[C::D - 1] >> xp) : 0u;
+    }
+    __syncthreads();
+
+    // 3) unions between runs of neighbouring rows.  Within a stretch where
+    //    neither row starts a new run both rows stay in the same two runs, so
+    //    only the first open bond of each stretch is joined.
 #pragma unroll
-                for (int d = 0; d < C::D; ++d) e += 2 * __popcll(eq_mask<C>(sm, ly, lz, d, g.wx)) - g.wx;
+    for (int dd = 1; dd < C::D; ++dd) {
+        const int step = (dd == 1) ? 1 : C::TY;
+        const bool inner = rowok && ((dd == 1) ? (ly < g.wy - 1) : (lz < g.wz - 1));
+        if (!inner) continue;
+        const uint64_t SSp = sm.SS[r + step];
+        const uint64_t V = opn[dd];
+        const uint64_t Mc = ~(SS | SSp);                 // neither row starts a run here
+        const uint64_t A = V | Mc;
+        const uint64_t carry = (A + V) ^ A ^ V;          // an open bond earlier in the stretch
+        uint64_t U = V & ~(Mc & carry) & (0xFFFFull << xp);
+        while (U) {
+            const int x = __builtin_ctzll(U);
+            U &= U - 1ull;
+            lds_join(sm.par, r * C::TX + start_at(SS, x), (r + step) * C::TX + start_at(SSp, x));
+        }
+    }
+    __syncthreads();
+
+    // 4) compress (one store per run start, of its root: the read-only walk is
+    //    safe against the other threads' stores) and border flags: a cluster
+    //    is a border cluster when one of its runs touches a near face or has
+    //    an open link leaving through a far face
+    if (partok) {
+        const bool nearrow = ly == 0 || (C::D == 3 && lz == 0);
+        uint64_t cross = 0;                                   // open links leaving through the far y / z faces
+        if (edgeY) cross |= opn[1];
+        if (edgeZ) cross |= opn[C::D - 1];
+        const int last = 63 - __clzll((long long)SS);
+        const bool xout = (opn[0] >> (g.wx - 1)) & 1ull;
+        uint64_t st = SS & (0xFFFFull << xp);
+        while (st) {
+            const int x = __builtin_ctzll(st);
+            st &= st - 1ull;
+            const int k = r * C::TX + x;
+            const int root = lds_root(sm.par, k);
+            lds_store(&sm.par[k], root);
+            bool b = nearrow || x == 0 || (x == last && xout);
+            if (!b && cross) {
+                const uint64_t later = SS & ~low_bits(x + 1);
+                const int xe = later ? __builtin_ctzll(later) - 1 : g.wx - 1;   // last site of the run
+                b = (cross & low_bits(xe + 1) & ~low_bits(x)) != 0ull;
             }
-            e_acc += e;
-            m_acc += m;
+            if (b) atomicOr(&sm.FB[root >> 5], 1u << (root & 31));
         }
     }
     __syncthreads();
 
-    // 4) unions across rows (y, z links inside the tile).  A link whose left
-    //    neighbour link joins the same two x-runs is implied and skipped.
-#pragma unroll 1
-    for (int i = 0; i < C::SITEIT; ++i) {
-        const int k = tid + kBlock * i;
-        const int x = k % C::TX, r = k / C::TX;
-        const int ly = r % C::TY, lz = r / C::TY;
-        if (x >= g.wx || ly >= g.wy || lz >= g.wz) continue;
-        if (ly < g.wy - 1 && ((sm.OPN[1][r] >> x) & 1ull)) {
-            const bool implied = x > 0 && (((sm.RR[r] & sm.OPN[1][r] & sm.RR[r + 1]) >> (x - 1)) & 1ull);
-            if (!implied) lds_unite(sm.par, k, k + C::TX);
+    // 5) tile-local labels (root | border flag) of the part and of its face
+    //    sites; border roots start their own global tree; the border bitmap
+    //    and the far x face's crossing bits
+    for (int w = tid; w < C::FBW; w += blockDim.x) R.fbits[(size_t)t * C::FBW + w] = sm.FB[w];
+    if (tid < C::W0) R.xbits[(size_t)t * C::XW + tid] = sm.XF[tid];
+    if (partok) {
+        uint16_t* nearf = R.face + (size_t)t * (2 * C::FT);
+        uint16_t* farf = nearf + C::FT;
+        const int rowk = r * C::TX;
+        auto label = [&](int x) {
+            const int root = sm.par[rowk + start_at(SS, x)];
+            return (uint32_t)root | (((sm.FB[root >> 5] >> (root & 31)) & 1u) << 15);
+        };
+        uint32_t cur = label(xp);
+        uint32_t pk[8];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int x = xp + j;
+            if (j > 0 && x < g.wx && ((SS >> x) & 1ull)) cur = label(x);
+            if (x < g.wx && ((SS >> x) & 1ull) && (cur & 0x7FFFu) == (uint32_t)(rowk + x) && (cur & kBorderFlag))
+                R.par[gi0 + (uint32_t)x] = (int32_t)(gi0 + (uint32_t)x);
+            if (j & 1) pk[j >> 1] |= cur << 16;
+            else pk[j >> 1] = cur;
         }
-        if (C::D == 3 && lz < g.wz - 1 && ((sm.OPN[C::D - 1][r] >> x) & 1ull)) {
-            const bool implied = x > 0 && (((sm.RR[r] & sm.OPN[C::D - 1][r] & sm.RR[r + C::TY]) >> (x - 1)) & 1ull);
-            if (!implied) lds_unite(sm.par, k, k + C::TX * C::TY);
-        }
-    }
-    __syncthreads();
-    // compress: one store per site, of its root.  Path halving here would race:
-    // a halving store can put an intermediate ancestor back over a root that
-    // another thread has just written.
-    for (int k = tid; k < C::TS; k += kBlock) {
-        const int root = lds_root(sm.par, k);
-        lds_store(&sm.par[k], root);
-    }
-    __syncthreads();
-
-    // 5) border clusters: touching a near face, or leaving through a far face
-#pragma unroll 2
-    for (int i = 0; i < C::SITEIT; ++i) {
-        const int k = tid + kBlock * i;
-        const int x = k % C::TX, r = k / C::TX;
-        const int ly = r % C::TY, lz = r / C::TY;
-        if (x >= g.wx || ly >= g.wy || lz >= g.wz) continue;
-        bool b = x == 0 || ly == 0 || (C::D == 3 && lz == 0);
-        b = b || (x == g.wx - 1 && ((sm.OPN[0][r] >> x) & 1ull)) || (ly == g.wy - 1 && ((sm.OPN[1][r] >> x) & 1ull));
-        if (C::D == 3) b = b || (lz == g.wz - 1 && ((sm.OPN[C::D - 1][r] >> x) & 1ull));
-        if (b) sm.flag[sm.par[k]] = 1;
-    }
-    __syncthreads();
-
-    // 6) tile-local labels; border roots start their own global tree
-#pragma unroll 4
-    for (int i = 0; i < C::SITEIT; ++i) {
-        const int k = tid + kBlock * i;
-        const int x = k % C::TX, r = k / C::TX;
-        const int ly = r % C::TY, lz = r / C::TY;
-        if (x >= g.wx || ly >= g.wy || lz >= g.wz) continue;
-        const int root = sm.par[k];
-        const uint32_t fl = sm.flag[root] ? kBorderFlag : 0u;
-        const uint32_t gi = (uint32_t)(g.x0 + x) + (uint32_t)L * ((uint32_t)(g.y0 + ly) + (uint32_t)L * (uint32_t)(g.z0 + lz));
-        R.lab16[gi] = (uint16_t)((uint32_t)root | fl);
-        if (root == k && fl) R.par[gi] = (int32_t)gi;
-    }
-    __syncthreads();
-}
-
-// --------------------------------------------------------------------------
-// K2: border merge over the tile's outgoing open links + flip table share.
-// --------------------------------------------------------------------------
-template <class C>
-__device__ __forceinline__ void face_site(const TileGeo& g, int d, int fb, int& lx, int& ly, int& lz)
-{
-    if (d == 0) {
-        lx = g.wx - 1;
-        ly = fb % C::TY;
-        lz = fb / C::TY;
-    } else if (d == 1) {
-        lx = fb % C::TX;
-        ly = g.wy - 1;
-        lz = fb / C::TX;
-    } else {
-        lx = fb % C::TX;
-        ly = fb / C::TX;
-        lz = g.wz - 1;
-    }
-}
-
-template <class C>
-__device__ void k2_tile(const SwRep& R, int t, uint32_t s)
-{
-    const int tid = threadIdx.x;
-    const TileGeo g = tile_geo<C>(R, t);
-    const int L = R.L;
-    const uint32_t* xb = R.xbits + (size_t)t * C::XW;
-    constexpr int FT = C::F0 + C::F1 + C::F2;
-    for (int it = tid; it < FT; it += kBlock) {
-        int d, fb, wbase;
-        if (it < C::F0) {
-            d = 0;
-            fb = it;
-            wbase = 0;
-        } else if (it < C::F0 + C::F1) {
-            d = 1;
-            fb = it - C::F0;
-            wbase = C::W0;
+        const int yfi = C::F0 + C::TX * lz + xp;          // y faces: index x + TX*lz
+        const int zfi = C::F0 + C::F1 + C::TX * ly + xp;  // z faces: index x + TX*ly
+        if (wide) {
+            const uint4 lo = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+            const uint4 hi = make_uint4(pk[4], pk[5], pk[6], pk[7]);
+            uint4* dst = reinterpret_cast<uint4*>(R.lab16 + gi0 + (uint32_t)xp);
+            dst[0] = lo;
+            dst[1] = hi;
+            if (ly == 0) { reinterpret_cast<uint4*>(nearf + yfi)[0] = lo; reinterpret_cast<uint4*>(nearf + yfi)[1] = hi; }
+            if (edgeY) { reinterpret_cast<uint4*>(farf + yfi)[0] = lo; reinterpret_cast<uint4*>(farf + yfi)[1] = hi; }
+            if (C::D == 3 && lz == 0) { reinterpret_cast<uint4*>(nearf + zfi)[0] = lo; reinterpret_cast<uint4*>(nearf + zfi)[1] = hi; }
+            if (edgeZ) { reinterpret_cast<uint4*>(farf + zfi)[0] = lo; reinterpret_cast<uint4*>(farf + zfi)[1] = hi; }
         } else {
-            d = 2;
-            fb = it - C::F0 - C::F1;
-            wbase = C::W0 + C::W1;
-        }
-        if (!((xb[wbase + (fb >> 5)] >> (fb & 31)) & 1u)) continue;
-        int lx, ly, lz;
-        face_site<C>(g, d, fb, lx, ly, lz);
-        const int ax = g.x0 + lx, ay = g.y0 + ly, az = g.z0 + lz;
-        const int bx = (d == 0) ? ((ax + 1 == L) ? 0 : ax + 1) : ax;
-        const int by = (d == 1) ? ((ay + 1 == L) ? 0 : ay + 1) : ay;
-        const int bz = (d == 2) ? ((az + 1 == L) ? 0 : az + 1) : az;
-        const uint32_t ga = (uint32_t)ax + (uint32_t)L * ((uint32_t)ay + (uint32_t)L * (uint32_t)az);
-        const uint32_t gb = (uint32_t)bx + (uint32_t)L * ((uint32_t)by + (uint32_t)L * (uint32_t)bz);
-        const uint32_t la = R.lab16[ga], lb = R.lab16[gb];
-        // the previous link along the face (first in-face axis) joining the
-        // same two tile-local clusters makes this union redundant
-        const int first = (d == 0) ? ly : lx;
-        if (first > 0) {
-            const int pfb = fb - 1;
-            if ((xb[wbase + (pfb >> 5)] >> (pfb & 31)) & 1u) {
-                const uint32_t step = (d == 0) ? (uint32_t)L : 1u;
-                const uint32_t pa = ga - step;
-                uint32_t pb;
-                if (d == 0) pb = gb - (uint32_t)L;
-                else pb = gb - 1u;
-                if (R.lab16[pa] == la && R.lab16[pb] == lb) continue;
+            for (int j = 0; j < np; ++j) {
+                const uint16_t v = (uint16_t)(pk[j >> 1] >> (16 * (j & 1)));
+                R.lab16[gi0 + (uint32_t)(xp + j)] = v;
+                if (ly == 0) nearf[yfi + j] = v;
+                if (edgeY) farf[yfi + j] = v;
+                if (C::D == 3 && lz == 0) nearf[zfi + j] = v;
+                if (edgeZ) farf[zfi + j] = v;
             }
         }
-        const uint32_t ra = tile_root_of<C>(R, ga, la);
-        const uint32_t rb = tile_root_of<C>(R, gb, lb);
-        if (ra == 0xFFFFFFFFu || rb == 0xFFFFFFFFu) continue;
-        g_unite(R, R.par, (int)ra, (int)rb);
+        if (q == 0) nearf[r] = (uint16_t)label(0);                     // x faces: index ly + TY*lz
+        if (xp <= g.wx - 1 && g.wx - 1 < xp + 16) farf[r] = (uint16_t)label(g.wx - 1);
     }
-    // flip bits of this sweep: table word 4b + w is word w of Philox(b, 0, s, FLIP)
-    const uint32_t nblk = (R.N + 127u) / 128u;
-    const uint32_t b0 = (uint32_t)(((uint64_t)t * nblk) / (uint32_t)R.ntiles);
-    const uint32_t b1 = (uint32_t)(((uint64_t)(t + 1) * nblk) / (uint32_t)R.ntiles);
-    const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
-    for (uint32_t b = b0 + (uint32_t)tid; b < b1; b += kBlock) {
-        const U4 r = philox10(b, 0u, s, kTagFlip, k0, k1);
-        uint4 v;
-        v.x = r.x;
-        v.y = r.y;
-        v.z = r.z;
-        v.w = r.w;
-        reinterpret_cast<uint4*>(R.fliptab)[b] = v;
-    }
+    __syncthreads();
 }
 
 // --------------------------------------------------------------------------
-// K3: cluster flip.  Each distinct tile-local root is resolved once (global
-// chase for border roots, flip bit from the table); sites then read their
-// root's result from LDS.  Optionally marks percolation coverage (PCC).
+// K2: border merge.  One work item per far-face site f of tile t: when its
+// link across the face is open, the two tile-local roots it joins are united
+// in the global union-find.  Face labels come from the compact face arrays.
+// --------------------------------------------------------------------------
+template <class C>
+__device__ __forceinline__ uint32_t tile_site_global(const SwRep& R, int ix, int iy, int iz, uint32_t lr)
+{
+    return local_to_global<C>(lr, ix * C::TX, iy * C::TY, iz * C::TZ, R.L);
+}
+
+template <class C>
+__device__ void k2_link(const SwRep& R, int t, int f)
+{
+    int d, fb, wbase;
+    if (f < C::F0) {
+        d = 0;
+        fb = f;
+        wbase = 0;
+    } else if (f < C::F0 + C::F1) {
+        d = 1;
+        fb = f - C::F0;
+        wbase = C::W0;
+    } else {
+        d = 2;
+        fb = f - C::F0 - C::F1;
+        wbase = C::W0 + C::W1;
+    }
+    const uint32_t* xb = R.xbits + (size_t)t * C::XW;
+    if (!((xb[wbase + (fb >> 5)] >> (fb & 31)) & 1u)) return;
+    const int ix = t % R.ntx, iy = (t / R.ntx) % R.nty, iz = t / (R.ntx * R.nty);
+    int jx = ix, jy = iy, jz = iz;
+    if (d == 0) jx = (ix + 1 == R.ntx) ? 0 : ix + 1;
+    else if (d == 1) jy = (iy + 1 == R.nty) ? 0 : iy + 1;
+    else jz = (iz + 1 == R.ntz) ? 0 : iz + 1;
+    const int tn = jx + R.ntx * (jy + R.nty * jz);
+    const uint16_t* farf = R.face + (size_t)t * (2 * C::FT) + C::FT;
+    const uint16_t* nearf = R.face + (size_t)tn * (2 * C::FT);
+    const uint32_t la = farf[f], lb = nearf[f];
+    // the previous link along the face (first in-face axis) joining the same
+    // two tile-local clusters makes this union redundant
+    const int first = (d == 0) ? fb % C::TY : fb % C::TX;
+    if (first > 0 && ((xb[wbase + ((fb - 1) >> 5)] >> ((fb - 1) & 31)) & 1u) && farf[f - 1] == la &&
+        nearf[f - 1] == lb)
+        return;
+    if (!(la & lb & kBorderFlag)) {                 // both ends are border roots' sites
+        flag_error(R, ERR_TILE_LABEL);
+        return;
+    }
+    const uint32_t ra = tile_site_global<C>(R, ix, iy, iz, la & 0x7FFFu);
+    const uint32_t rb = tile_site_global<C>(R, jx, jy, jz, lb & 0x7FFFu);
+    if (ra >= R.N || rb >= R.N) {
+        flag_error(R, ERR_TILE_LABEL);
+        return;
+    }
+    g_unite(R, R.par, (int)ra, (int)rb);
+}
+
+// --------------------------------------------------------------------------
+// K3a: border roots.  Word w of tile t's border bitmap lists 32 tile-local
+// sites; each border root among them finds its cluster root (the smallest
+// site index of the cluster), takes it as parent, and the cluster's flip bit
+// is recorded for the flip pass.
+// --------------------------------------------------------------------------
+template <class C>
+__device__ void k3a_word(const SwRep& R, int t, int w, uint32_t s)
+{
+    uint32_t m = R.fbits[(size_t)t * C::FBW + w];
+    uint32_t out = 0;
+    if (m) {
+        const int ix = t % R.ntx, iy = (t / R.ntx) % R.nty, iz = t / (R.ntx * R.nty);
+        const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
+        while (m) {
+            const int b = __ffs(m) - 1;
+            m &= m - 1u;
+            const uint32_t gi = tile_site_global<C>(R, ix, iy, iz, (uint32_t)(w * 32 + b));
+            if (gi >= R.N) {
+                flag_error(R, ERR_TILE_LABEL);
+                continue;
+            }
+            const uint32_t root = ro_find(R, gi);
+            if (root != gi) R.par[gi] = (int32_t)root;
+            out |= flip_bit(root, s, k0, k1) << b;
+        }
+    }
+    R.bflip[(size_t)t * C::FBW + w] = out;
+}
+
+// --------------------------------------------------------------------------
+// K3b: cluster flip.  A site's tile-local root is either interior (its own
+// index is the cluster label, its flip bit comes from the tile's own row of
+// flip bits) or a border root (flip bit from K3a).  Optionally writes the
+// final labels and marks percolation coverage (PCC).
 // --------------------------------------------------------------------------
 template <class C>
 struct K3Smem {
-    uint32_t res[C::TS];   // (cluster root << 1) | new-spin bit, per tile-local root
-    uint8_t need[C::TS];   // 0: unused, 1: interior root, 2: border root
+    uint64_t RF[C::NR];     // flip bits of the tile's own sites, one mask per row
+    uint32_t BF[C::FBW];    // flip bits of the tile's border roots
 };
+
+template <class C>
+__device__ __forceinline__ void pcc_mark(const SwRep& R, uint32_t root, const uint32_t crd[3], uint64_t tag,
+                                         uint32_t bw, uint32_t nslots)
+{
+#pragma unroll
+    for (int a = 0; a < C::D; ++a) {
+        const uint64_t c = R.cand[(size_t)a * R.N + root];
+        if ((c & 0xFFFFFFFF00000000ull) != tag) continue;
+        const uint32_t slot = ~(uint32_t)c;
+        if (slot >= nslots) {
+            flag_error(R, ERR_SLOT);
+            continue;
+        }
+        uint32_t* bm = R.bmp + ((size_t)a * nslots + slot) * bw;
+        atomicOr(&bm[crd[a] >> 5], 1u << (crd[a] & 31u));
+    }
+}
+
+// new spin byte of the site with tile-local index k and stored label v;
+// writes the final label / coverage marks when asked for
+template <class C>
+__device__ __forceinline__ uint32_t k3_site(const SwRep& R, const K3Smem<C>& sm, const TileGeo& g, uint32_t v, int k,
+                                            uint32_t gi, bool labels, bool pcc, uint64_t tag, uint32_t bw,
+                                            uint32_t nslots)
+{
+    const uint32_t lr = v & 0x7FFFu;
+    if (lr > (uint32_t)k) {                 // a tile root precedes its sites
+        flag_error(R, ERR_TILE_LABEL);
+        return 0xFFu;
+    }
+    const bool border = (v & kBorderFlag) != 0;
+    const uint32_t bit = border ? (sm.BF[lr >> 5] >> (lr & 31u)) & 1u : (uint32_t)(sm.RF[lr / C::TX] >> (lr % C::TX)) & 1u;
+    if (labels || pcc) {
+        uint32_t root = local_to_global<C>(lr, g.x0, g.y0, g.z0, R.L);
+        if (border) root = (uint32_t)R.par[root];   // K3a made it the cluster root
+        if (root >= R.N) {
+            flag_error(R, ERR_PARENT);
+            root = 0;
+        }
+        if (labels) R.lab32[gi] = (int32_t)root;
+        if (pcc) {
+            const uint32_t crd[3] = {(uint32_t)(g.x0 + k % C::TX), (uint32_t)(g.y0 + (k / C::TX) % C::TY),
+                                     (uint32_t)(g.z0 + k / (C::TX * C::TY))};
+            pcc_mark<C>(R, root, crd, tag, bw, nslots);
+        }
+    }
+    return bit ? 0x01u : 0xFFu;
+}
 
 template <class C>
 __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
@@ -659,65 +886,44 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
     const int tid = threadIdx.x;
     const TileGeo g = tile_geo<C>(R, t);
     const uint32_t L = (uint32_t)R.L;
-    for (int k = tid; k < C::TS; k += kBlock) sm.need[k] = 0;
-    __syncthreads();
-    uint16_t v[C::SITEIT];
-#pragma unroll
-    for (int i = 0; i < C::SITEIT; ++i) {
-        const int k = tid + kBlock * i;
-        const int x = k % C::TX, r = k / C::TX;
-        const int ly = r % C::TY, lz = r / C::TY;
-        v[i] = 0xFFFFu;
-        if (x >= g.wx || ly >= g.wy || lz >= g.wz) continue;
-        const uint32_t gi = (uint32_t)(g.x0 + x) + L * ((uint32_t)(g.y0 + ly) + L * (uint32_t)(g.z0 + lz));
-        v[i] = R.lab16[gi];
-        if ((uint32_t)(v[i] & 0x7FFFu) > (uint32_t)k) {   // a tile root precedes its sites
-            flag_error(R, ERR_TILE_LABEL);
-            v[i] = 0xFFFFu;
-        }
+    const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
+    if (tid < C::NR) {
+        const int ly = tid % C::TY, lz = tid / C::TY;
+        uint64_t m = 0;
+        if (ly < g.wy && lz < g.wz)
+            m = row_flips((uint32_t)g.x0 + L * ((uint32_t)(g.y0 + ly) + L * (uint32_t)(g.z0 + lz)), g.wx, s, k0, k1);
+        sm.RF[tid] = m;
     }
-#pragma unroll
-    for (int i = 0; i < C::SITEIT; ++i)
-        if (v[i] != 0xFFFFu) sm.need[v[i] & 0x7FFFu] = (v[i] & kBorderFlag) ? 2 : 1;
+    for (int w = tid; w < C::FBW; w += kBlock) sm.BF[w] = R.bflip[(size_t)t * C::FBW + w];
     __syncthreads();
-    for (int k = tid; k < C::TS; k += kBlock) {
-        const uint8_t nd = sm.need[k];
-        if (!nd) continue;
-        uint32_t r = local_to_global<C>((uint32_t)k, g.x0, g.y0, g.z0, (int)L);
-        if (nd == 2) r = ro_find(R, r);
-        const uint32_t bit = (R.fliptab[r >> 5] >> (r & 31u)) & 1u;
-        sm.res[k] = (r << 1) | bit;
-    }
-    __syncthreads();
+    const bool labels = R.lab32 != nullptr;
     const bool pcc = (R.flags & FLAG_PCC) != 0;
     const uint64_t tag = (uint64_t)(s + 1u) << 32;
     const uint32_t bw = (L + 31u) / 32u;               // bitmap words per candidate
     const uint32_t nslots = (C::D == 3) ? L * L : L;   // candidates per axis
-#pragma unroll
-    for (int i = 0; i < C::SITEIT; ++i) {
-        if (v[i] == 0xFFFFu) continue;
-        const int k = tid + kBlock * i;
-        const int x = k % C::TX, r = k / C::TX;
-        const int ly = r % C::TY, lz = r / C::TY;
-        const uint32_t gi = (uint32_t)(g.x0 + x) + L * ((uint32_t)(g.y0 + ly) + L * (uint32_t)(g.z0 + lz));
-        const uint32_t q = sm.res[v[i] & 0x7FFFu];
-        const uint32_t root = q >> 1;
-        R.spins[gi] = (q & 1u) ? (int8_t)1 : (int8_t)-1;
-        if (R.lab32) R.lab32[gi] = (int32_t)root;
-        if (pcc) {
-            const uint32_t crd[3] = {(uint32_t)(g.x0 + x), (uint32_t)(g.y0 + ly), (uint32_t)(g.z0 + lz)};
-#pragma unroll
-            for (int a = 0; a < C::D; ++a) {
-                const uint64_t c = R.cand[(size_t)a * R.N + root];
-                if ((c & 0xFFFFFFFF00000000ull) != tag) continue;
-                const uint32_t slot = ~(uint32_t)c;
-                if (slot >= nslots) {
-                    flag_error(R, ERR_SLOT);
-                    continue;
-                }
-                uint32_t* bm = R.bmp + ((size_t)a * nslots + slot) * bw;
-                atomicOr(&bm[crd[a] >> 5], 1u << (crd[a] & 31u));
-            }
+    if ((L & 3u) == 0) {
+        // four sites per thread: every row and the tile width are multiples of 4
+        constexpr int QR = C::TX / 4;
+        for (int qd = tid; qd < C::TS / 4; qd += kBlock) {
+            const int r = qd / QR, xq = (qd % QR) * 4;
+            const int ly = r % C::TY, lz = r / C::TY;
+            if (ly >= g.wy || lz >= g.wz || xq >= g.wx) continue;
+            const uint32_t gi = (uint32_t)(g.x0 + xq) + L * ((uint32_t)(g.y0 + ly) + L * (uint32_t)(g.z0 + lz));
+            const uint2 v = *reinterpret_cast<const uint2*>(R.lab16 + gi);
+            const int k = r * C::TX + xq;
+            uint32_t out = k3_site<C>(R, sm, g, v.x & 0xFFFFu, k, gi, labels, pcc, tag, bw, nslots);
+            out |= k3_site<C>(R, sm, g, v.x >> 16, k + 1, gi + 1, labels, pcc, tag, bw, nslots) << 8;
+            out |= k3_site<C>(R, sm, g, v.y & 0xFFFFu, k + 2, gi + 2, labels, pcc, tag, bw, nslots) << 16;
+            out |= k3_site<C>(R, sm, g, v.y >> 16, k + 3, gi + 3, labels, pcc, tag, bw, nslots) << 24;
+            *reinterpret_cast<uint32_t*>(R.spins + gi) = out;
+        }
+    } else {
+        for (int k = tid; k < C::TS; k += kBlock) {
+            const int xk = k % C::TX, r = k / C::TX;
+            const int ly = r % C::TY, lz = r / C::TY;
+            if (ly >= g.wy || lz >= g.wz || xk >= g.wx) continue;
+            const uint32_t gi = (uint32_t)(g.x0 + xk) + L * ((uint32_t)(g.y0 + ly) + L * (uint32_t)(g.z0 + lz));
+            R.spins[gi] = (int8_t)k3_site<C>(R, sm, g, R.lab16[gi], k, gi, labels, pcc, tag, bw, nslots);
         }
     }
     __syncthreads();

@@ -18,7 +18,8 @@ int device_cu_count();
 uint64_t device_wallclock_hz();
 
 int launch_k1(const SwRep& h, SwRep* d, uint32_t s, int64_t* em, hipStream_t stream, int per_cu);
-int launch_k2(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream, int per_cu);
+int launch_k2(const SwRep& h, SwRep* d, hipStream_t stream);
+int launch_k3a(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream);
 int launch_k3(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream, int per_cu);
 int launch_cand(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream);
 int launch_perc(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream);
@@ -34,5 +35,7 @@ int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, i
 int shape_count(int dim);
 int shape_extents(int dim, int id, int* tx, int* ty, int* tz);
 int shape_xwords(int dim, int id);
+int shape_fbw(int dim, int id);
+int shape_ft(int dim, int id);
 
 }  // namespace sw

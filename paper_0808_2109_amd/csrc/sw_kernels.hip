@@ -1,10 +1,11 @@
 // sw_kernels.hip -- the HIP kernels of the sweep and their host launchers.
 //
-// Plain path: one launch per phase and replica (K1, K2, K3, and for PCC the
-// candidate, coverage and feedback kernels), each a grid of workgroups that
-// walk contiguous chunks of tiles.  Batched path: each phase is one launch
-// over the tiles of all replicas, and the launches of many sweeps are replayed
-// from one hipGraph.
+// Plain path: one launch per phase and replica (K1, K2, K3a, K3b, and for
+// PCC the candidate, coverage and feedback kernels).  K1 and K3b are grids of
+// workgroups that walk contiguous chunks of tiles; K2 and K3a run one thread
+// per face site / bitmap word of every tile.  Batched path: each phase is one
+// launch over the tiles of all replicas, and the launches of many sweeps are
+// replayed from one hipGraph.
 #include "sw_device.hpp"
 #include "sw_internal.hpp"
 
@@ -12,20 +13,17 @@ namespace sw {
 
 // tile shapes: (id, dim, TX, TY, TZ).  The batched kernels are compiled for
 // the pairs (2D shape i, 3D shape i).
-#define SW_SHAPES_2D(X) X(0, 2, 64, 32, 1) X(1, 2, 64, 16, 1) X(2, 2, 64, 64, 1) X(3, 2, 32, 32, 1)
-#define SW_SHAPES_3D(X) X(0, 3, 32, 8, 8) X(1, 3, 32, 16, 4) X(2, 3, 64, 4, 8) X(3, 3, 32, 4, 16)
+// Every shape has 64 rows (TY * TZ), one per lane of the K1 wave.
+#define SW_SHAPES_2D(X) X(0, 2, 64, 64, 1) X(1, 2, 32, 64, 1)
+#define SW_SHAPES_3D(X) X(0, 3, 32, 8, 8) X(1, 3, 32, 16, 4)
 #define SW_SHAPES(X) SW_SHAPES_2D(X) SW_SHAPES_3D(X)
-using Eng0_2D = TileCfg<2, 64, 32, 1>;
+using Eng0_2D = TileCfg<2, 64, 64, 1>;
 using Eng0_3D = TileCfg<3, 32, 8, 8>;
-using Eng1_2D = TileCfg<2, 64, 16, 1>;
+using Eng1_2D = TileCfg<2, 32, 64, 1>;
 using Eng1_3D = TileCfg<3, 32, 16, 4>;
-using Eng2_2D = TileCfg<2, 64, 64, 1>;
-using Eng2_3D = TileCfg<3, 64, 4, 8>;
-using Eng3_2D = TileCfg<2, 32, 32, 1>;
-using Eng3_3D = TileCfg<3, 32, 4, 16>;
-#define SW_ENGINE_PAIRS(X) X(0, Eng0_2D, Eng0_3D) X(1, Eng1_2D, Eng1_3D) X(2, Eng2_2D, Eng2_3D) X(3, Eng3_2D, Eng3_3D)
+#define SW_ENGINE_PAIRS(X) X(0, Eng0_2D, Eng0_3D) X(1, Eng1_2D, Eng1_3D)
 
-constexpr int kNumShapes = 4;
+constexpr int kNumShapes = 2;
 
 // XCD-aware chunking: workgroup b runs on XCD b % 8.  Giving XCD k the k-th
 // eighth of the (replica, tile) work list keeps a band of neighbouring tiles
@@ -64,32 +62,55 @@ __device__ __forceinline__ void block_sum2(int64_t& a, int64_t& b, int64_t* red)
 // ---------------------------------------------------------------------------
 // Plain kernels.
 // ---------------------------------------------------------------------------
-template <class C>
-__global__ __launch_bounds__(kBlock) void k1_kernel(const SwRep* Rd, uint32_t s, int64_t* em)
+// sum of a and b over the wave, then one atomic add per wave
+__device__ __forceinline__ void wave_flush_em(int64_t a, int64_t b, int64_t* dst)
 {
-    __shared__ K1Smem<C> sm;
-    __shared__ int64_t red[2 * kBlock / 64];
-    const SwRep R = *Rd;
-    int t0, t1;
-    chunk_of(R.ntiles, t0, t1);
-    int64_t e = 0, m = 0;
-    for (int t = t0; t < t1; ++t) k1_tile<C>(R, t, s, R.thr, sm, em != nullptr, e, m);
-    if (em) {
-        block_sum2(e, m, red);
-        if (threadIdx.x == 0 && t1 > t0) {
-            atomicAdd((unsigned long long*)&em[0], (unsigned long long)e);
-            atomicAdd((unsigned long long*)&em[1], (unsigned long long)m);
-        }
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off, 64);
+        b += __shfl_down(b, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd((unsigned long long*)&dst[0], (unsigned long long)a);
+        atomicAdd((unsigned long long*)&dst[1], (unsigned long long)b);
     }
 }
 
+// K1: one workgroup of K1Cfg<C>::NT threads per tile, grid = ntiles; block b
+// runs on XCD b % 8, which gets the b % 8-th eighth of the tiles
+__device__ __forceinline__ int xcd_item(int nitems)
+{
+    int i0, i1;
+    chunk_of(nitems, i0, i1);
+    return i0;
+}
+
 template <class C>
-__global__ __launch_bounds__(kBlock) void k2_kernel(const SwRep* Rd, uint32_t s)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k1_kernel(const SwRep* Rd,
+                                                                                           uint32_t s, int64_t* em)
+{
+    __shared__ K1Smem<C> sm;
+    const SwRep R = *Rd;
+    int64_t e = 0, m = 0;
+    k1_tile<C>(R, xcd_item(R.ntiles), s, R.thr, sm, em != nullptr, e, m);
+    if (em) wave_flush_em(e, m, em);
+}
+
+template <class C>
+__global__ __launch_bounds__(kBlock) void k2_kernel(const SwRep* Rd)
 {
     const SwRep R = *Rd;
-    int t0, t1;
-    chunk_of(R.ntiles, t0, t1);
-    for (int t = t0; t < t1; ++t) k2_tile<C>(R, t, s);
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (gid >= (int64_t)R.ntiles * C::FT) return;
+    k2_link<C>(R, (int)(gid / C::FT), (int)(gid % C::FT));
+}
+
+template <class C>
+__global__ __launch_bounds__(kBlock) void k3a_kernel(const SwRep* Rd, uint32_t s)
+{
+    const SwRep R = *Rd;
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (gid >= (int64_t)R.ntiles * C::FBW) return;
+    k3a_word<C>(R, (int)(gid / C::FBW), (int)(gid % C::FBW), s);
 }
 
 template <class C>
@@ -264,56 +285,58 @@ __device__ __forceinline__ void flush_em(int64_t e, int64_t m, int64_t* dst, int
     }
 }
 
-// K1 over the work list, with E, M of the incoming configuration summed per replica
+// K1 over the work list: one workgroup per item (grid = nitems, as many
+// threads as the larger of the two tiles needs), with E, M of the incoming
+// configuration added to the replica's series entry
 template <class C2, class C3>
-__global__ __launch_bounds__(kBlock) void kb1_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
-                                                     int n_sweeps)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void kb1_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
+                                                    int n_sweeps)
 {
     __shared__ __align__(16) char smem[cmax2(sizeof(K1Smem<C2>), sizeof(K1Smem<C3>))];
-    __shared__ int64_t red[2 * kBlock / 64];
-    int i0, i1;
-    chunk_of(nitems, i0, i1);
-    int cur = -1;
-    int64_t e = 0, m = 0;
+    const int i = blockIdx.x;
+    if (i >= nitems) return;
+    const SwRep& R = reps[items[i].rep];
+    uint32_t s;
+    if (!rep_runs(R, it, n_sweeps, s)) return;
     int64_t* dst = nullptr;
-    for (int i = i0; i <= i1; ++i) {
-        const int rep = (i < i1) ? items[i].rep : -2;
-        if (rep != cur) {
-            if (cur >= 0 && dst) flush_em(e, m, dst, red);   // sums of the previous replica
-            e = m = 0;
-            dst = nullptr;
-            cur = rep;
-            if (rep >= 0) {
-                const SwRep& R = reps[rep];
-                uint32_t s;
-                if (rep_runs(R, it, n_sweeps, s) && (R.flags & FLAG_SERIES) && s >= 1 && (it > 0 || R.measured < R.sweep))
-                    dst = R.series + 2 * (size_t)(s - 1);
-            }
-        }
-        if (i == i1) break;
-        const SwRep& R = reps[rep];
-        uint32_t s;
-        if (!rep_runs(R, it, n_sweeps, s)) continue;
-        if (R.dim == 2)
-            k1_tile<C2>(R, items[i].tile, s, R.thr, *reinterpret_cast<K1Smem<C2>*>(smem), dst != nullptr, e, m);
-        else
-            k1_tile<C3>(R, items[i].tile, s, R.thr, *reinterpret_cast<K1Smem<C3>*>(smem), dst != nullptr, e, m);
-    }
+    if ((R.flags & FLAG_SERIES) && s >= 1 && (it > 0 || R.measured < R.sweep)) dst = R.series + 2 * (size_t)(s - 1);
+    int64_t e = 0, m = 0;
+    if (R.dim == 2)
+        k1_tile<C2>(R, items[i].tile, s, R.thr, *reinterpret_cast<K1Smem<C2>*>(smem), dst != nullptr, e, m);
+    else
+        k1_tile<C3>(R, items[i].tile, s, R.thr, *reinterpret_cast<K1Smem<C3>*>(smem), dst != nullptr, e, m);
+    if (dst) wave_flush_em(e, m, dst);
 }
 
+// K2 and K3a: one workgroup per work item (launched with grid = nitems)
 template <class C2, class C3>
 __global__ __launch_bounds__(kBlock) void kb2_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
                                                      int n_sweeps)
 {
-    int i0, i1;
-    chunk_of(nitems, i0, i1);
-    for (int i = i0; i < i1; ++i) {
-        const SwRep& R = reps[items[i].rep];
-        uint32_t s;
-        if (!rep_runs(R, it, n_sweeps, s)) continue;
-        if (R.dim == 2) k2_tile<C2>(R, items[i].tile, s);
-        else k2_tile<C3>(R, items[i].tile, s);
-    }
+    const int i = blockIdx.x;
+    if (i >= nitems) return;
+    const SwRep& R = reps[items[i].rep];
+    uint32_t s;
+    if (!rep_runs(R, it, n_sweeps, s)) return;
+    if (R.dim == 2)
+        for (int f = threadIdx.x; f < C2::FT; f += kBlock) k2_link<C2>(R, items[i].tile, f);
+    else
+        for (int f = threadIdx.x; f < C3::FT; f += kBlock) k2_link<C3>(R, items[i].tile, f);
+}
+
+template <class C2, class C3>
+__global__ __launch_bounds__(kBlock) void kb3a_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
+                                                      int n_sweeps)
+{
+    const int i = blockIdx.x;
+    if (i >= nitems) return;
+    const SwRep& R = reps[items[i].rep];
+    uint32_t s;
+    if (!rep_runs(R, it, n_sweeps, s)) return;
+    if (R.dim == 2)
+        for (int w = threadIdx.x; w < C2::FBW; w += kBlock) k3a_word<C2>(R, items[i].tile, w, s);
+    else
+        for (int w = threadIdx.x; w < C3::FBW; w += kBlock) k3a_word<C3>(R, items[i].tile, w, s);
 }
 
 template <class C2, class C3>
@@ -446,21 +469,38 @@ static int grid_for(int ntiles, int per_cu)
 
 int launch_k1(const SwRep& h, SwRep* d, uint32_t s, int64_t* em, hipStream_t stream, int per_cu)
 {
-    const int grid = grid_for(h.ntiles, per_cu);
+    (void)per_cu;
+    const int grid = h.ntiles;
     switch (h.dim * 16 + h.shape) {
-#define L1(id, D, X, Y, Z) SW_LAUNCH_CASE(id, D, X, Y, Z, k1_kernel, d, s, em)
+#define L1(id, D, X, Y, Z)                                                                  \
+    case (D * 16 + id): {                                                                  \
+        using C = TileCfg<D, X, Y, Z>;                                                     \
+        hipLaunchKernelGGL(k1_kernel<C>, dim3(grid), dim3(K1Cfg<C>::NT), 0, stream, d, s, em); \
+        break;                                                                             \
+    }
         SW_SHAPES(L1)
         default: return -1;
     }
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-int launch_k2(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream, int per_cu)
+int launch_k2(const SwRep& h, SwRep* d, hipStream_t stream)
 {
-    const int grid = grid_for(h.ntiles, per_cu);
+    const int grid = (int)(((int64_t)h.ntiles * h.ft + kBlock - 1) / kBlock);
     switch (h.dim * 16 + h.shape) {
-#define L2(id, D, X, Y, Z) SW_LAUNCH_CASE(id, D, X, Y, Z, k2_kernel, d, s)
+#define L2(id, D, X, Y, Z) SW_LAUNCH_CASE(id, D, X, Y, Z, k2_kernel, d)
         SW_SHAPES(L2)
+        default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int launch_k3a(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream)
+{
+    const int grid = (int)(((int64_t)h.ntiles * h.fbw + kBlock - 1) / kBlock);
+    switch (h.dim * 16 + h.shape) {
+#define L3A(id, D, X, Y, Z) SW_LAUNCH_CASE(id, D, X, Y, Z, k3a_kernel, d, s)
+        SW_SHAPES(L3A)
         default: return -1;
     }
     return hipGetLastError() == hipSuccess ? 0 : -3;
@@ -531,8 +571,9 @@ int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, i
 #define SW_BATCH(i, C2, C3)                                                                                          \
     case i:                                                                                                          \
         for (int it = 0; it < n_sweeps; ++it) {                                                                      \
-            hipLaunchKernelGGL((kb1_kernel<C2, C3>), dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
-            hipLaunchKernelGGL((kb2_kernel<C2, C3>), dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
+            hipLaunchKernelGGL((kb1_kernel<C2, C3>), dim3(nitems), dim3(max(K1Cfg<C2>::NT, K1Cfg<C3>::NT)), 0, stream, reps, items, nitems, it, n_sweeps); \
+            hipLaunchKernelGGL((kb2_kernel<C2, C3>), dim3(nitems), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
+            hipLaunchKernelGGL((kb3a_kernel<C2, C3>), dim3(nitems), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
             if (any_pcc)                                                                                             \
                 hipLaunchKernelGGL((kbc_kernel<C2, C3>), dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
             hipLaunchKernelGGL((kb3_kernel<C2, C3>), dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
@@ -574,6 +615,22 @@ int shape_xwords(int dim, int id)
 #define SW_XW(i, D, X, Y, Z) \
     if (dim == D && id == i) return TileCfg<D, X, Y, Z>::XW;
     SW_SHAPES(SW_XW)
+    return -1;
+}
+
+int shape_fbw(int dim, int id)
+{
+#define SW_FBW(i, D, X, Y, Z) \
+    if (dim == D && id == i) return TileCfg<D, X, Y, Z>::FBW;
+    SW_SHAPES(SW_FBW)
+    return -1;
+}
+
+int shape_ft(int dim, int id)
+{
+#define SW_FT(i, D, X, Y, Z) \
+    if (dim == D && id == i) return TileCfg<D, X, Y, Z>::FT;
+    SW_SHAPES(SW_FT)
     return -1;
 }
 

@@ -124,6 +124,15 @@ void fill_geometry(SwRep& h, int shape)
     h.ntz = (h.dim == 3) ? (h.L + tz - 1) / tz : 1;
     h.ntiles = h.ntx * h.nty * h.ntz;
     h.xwords = shape_xwords(h.dim, shape);
+    h.fbw = shape_fbw(h.dim, shape);
+    h.ft = shape_ft(h.dim, shape);
+}
+
+// per-tile buffers: crossing bits, border bitmaps (roots and their flip bits), face labels
+static uint64_t tile_bytes(const SwRep& h)
+{
+    const uint64_t nt = (uint64_t)h.ntiles;
+    return nt * (uint64_t)h.xwords * 4 + 2 * nt * (uint64_t)h.fbw * 4 + nt * 2 * (uint64_t)h.ft * 2;
 }
 
 uint64_t footprint_bytes(const sw_params* p, int shape)
@@ -135,8 +144,7 @@ uint64_t footprint_bytes(const sw_params* p, int shape)
     fill_geometry(h, shape);
     uint64_t b = n * (1 + 2 + 4);                            // spins, lab16, par
     if (p->flags & (SW_KEEP_LABELS | SW_PCC)) b += 4 * n;    // lab32
-    b += (uint64_t)h.ntiles * (uint64_t)h.xwords * 4;        // crossing bits
-    b += ((n + 127) / 128) * 16;                             // flip table
+    b += tile_bytes(h);                                      // crossing bits, border bitmaps, face labels
     b += 64;                                                 // accumulators
     if (p->flags & SW_PCC) {
         const uint64_t L = (uint64_t)p->L;
@@ -172,6 +180,27 @@ static void dfree(void* p)
     if (p) (void)hipFree(p);
 }
 
+// the per-tile buffers of a descriptor whose geometry is filled in
+static int alloc_tile_buffers(SwRep& h)
+{
+    const size_t nt = (size_t)h.ntiles;
+    h.xbits = h.fbits = h.bflip = nullptr;
+    h.face = nullptr;
+    int rc = dmalloc((void**)&h.xbits, nt * h.xwords * 4, "crossing bits");
+    if (!rc) rc = dmalloc((void**)&h.fbits, nt * h.fbw * 4, "border bitmaps");
+    if (!rc) rc = dmalloc((void**)&h.bflip, nt * h.fbw * 4, "border flip bits");
+    if (!rc) rc = dmalloc((void**)&h.face, nt * 2 * h.ft * 2, "face labels");
+    if (rc) {
+        dfree(h.xbits);
+        dfree(h.fbits);
+        dfree(h.bflip);
+        dfree(h.face);
+        h.xbits = h.fbits = h.bflip = nullptr;
+        h.face = nullptr;
+    }
+    return rc;
+}
+
 void replica_free(ReplicaH& r)
 {
     if (r.own_spins) dfree(r.h.spins);
@@ -179,7 +208,9 @@ void replica_free(ReplicaH& r)
     dfree(r.h.par);
     dfree(r.h.lab32);
     dfree(r.h.xbits);
-    dfree(r.h.fliptab);
+    dfree(r.h.fbits);
+    dfree(r.h.bflip);
+    dfree(r.h.face);
     dfree(r.h.series);
     dfree(r.h.acc);
     dfree(r.h.cand);
@@ -190,7 +221,8 @@ void replica_free(ReplicaH& r)
     r.h.spins = nullptr;
     r.h.lab16 = nullptr;
     r.h.par = r.h.lab32 = r.h.pflag = r.h.perc_trace = nullptr;
-    r.h.xbits = r.h.fliptab = r.h.bmp = nullptr;
+    r.h.xbits = r.h.fbits = r.h.bflip = r.h.bmp = nullptr;
+    r.h.face = nullptr;
     r.h.series = r.h.acc = nullptr;
     r.h.cand = nullptr;
     r.h.p_trace = nullptr;
@@ -226,8 +258,7 @@ int replica_alloc(ReplicaH& r, const sw_params* p, int shape, hipStream_t stream
     if ((rc = dmalloc((void**)&h.par, 4 * n, "union-find parents"))) goto bad;
     if (h.flags & (FLAG_KEEP | FLAG_PCC))
         if ((rc = dmalloc((void**)&h.lab32, 4 * n, "labels"))) goto bad;
-    if ((rc = dmalloc((void**)&h.xbits, (size_t)h.ntiles * h.xwords * 4, "crossing bits"))) goto bad;
-    if ((rc = dmalloc((void**)&h.fliptab, ((n + 127) / 128) * 16, "flip table"))) goto bad;
+    if ((rc = alloc_tile_buffers(h))) goto bad;
     if ((rc = dmalloc((void**)&h.acc, 64, "accumulators"))) goto bad;
     if (h.flags & FLAG_SERIES) {
         h.series_cap = p->series_cap ? p->series_cap : 1024;
@@ -449,7 +480,8 @@ int plain_sweep(sw_lattice* h, int r, int32_t n)
             m.measured = s;
         }
         TIMED(h, 0, launch_k1(m, d, s, em, h->stream, h->per_cu[0]));
-        TIMED(h, 1, launch_k2(m, d, s, h->stream, h->per_cu[1]));
+        TIMED(h, 1, launch_k2(m, d, h->stream));
+        TIMED(h, 6, launch_k3a(m, d, s, h->stream));
         if (pcc) TIMED(h, 3, launch_cand(m, d, s, h->stream));
         TIMED(h, 2, launch_k3(m, d, s, h->stream, h->per_cu[2]));
         if (pcc) TIMED(h, 3, launch_perc(m, d, s, h->stream));
@@ -849,7 +881,7 @@ int sw_set_timing(sw_lattice* h, int32_t enable)
     int rc = timing_collect(h);
     if (rc) return rc;
     h->timing = enable != 0;
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < kPhases; ++k) {
         h->ms[k] = 0.0;
         h->launches[k] = 0;
     }
@@ -861,7 +893,7 @@ int sw_get_timing(sw_lattice* h, double* ms, int64_t* launches, int32_t n)
     if (!h) return fail(SW_EINVAL, "null handle");
     int rc = timing_collect(h);
     if (rc) return rc;
-    for (int k = 0; k < n && k < 6; ++k) {
+    for (int k = 0; k < n && k < kPhases; ++k) {
         if (ms) ms[k] = h->ms[k];
         if (launches) launches[k] = h->launches[k];
     }
@@ -880,12 +912,13 @@ int sw_set_tile_shape(sw_lattice* h, int32_t replica, int32_t shape)
     if (shape == r.h.shape) return SW_OK;
     SwRep probe = r.h;
     fill_geometry(probe, shape);
-    uint32_t* nx = nullptr;
-    rc = dmalloc((void**)&nx, (size_t)probe.ntiles * probe.xwords * 4, "crossing bits");
+    rc = alloc_tile_buffers(probe);
     if (rc) return rc;
     dfree(r.h.xbits);
-    fill_geometry(r.h, shape);
-    r.h.xbits = nx;
+    dfree(r.h.fbits);
+    dfree(r.h.bflip);
+    dfree(r.h.face);
+    r.h = probe;
     h->items_dirty = true;
     return push_desc(h, replica);
 }

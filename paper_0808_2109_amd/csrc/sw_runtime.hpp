@@ -24,6 +24,9 @@ struct TimedLaunch {
     hipEvent_t a, b;
 };
 
+// timed phases: 0 K1, 1 K2, 2 K3b, 3 PCC, 4 measurement, 5 batched sweeps, 6 K3a
+constexpr int kPhases = 7;
+
 int fail(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
 uint64_t threshold_from_p(double p);
@@ -51,8 +54,8 @@ struct sw_lattice {
     bool timing = false;
     std::vector<sw::TimedLaunch> pending;
     std::vector<hipEvent_t> event_pool;
-    double ms[6] = {0, 0, 0, 0, 0, 0};
-    int64_t launches[6] = {0, 0, 0, 0, 0, 0};
+    double ms[sw::kPhases] = {};
+    int64_t launches[sw::kPhases] = {};
     // batched execution (work list of all replicas' tiles, replayed graph)
     sw::EngineItem* items = nullptr;
     size_t items_cap = 0;

@@ -21,7 +21,7 @@ SW_OK, SW_EINVAL, SW_ENOMEM, SW_EHIP, SW_EBUSY, SW_ENOTFOUND, SW_ECANCELLED, SW_
 SW_RECORD_SERIES, SW_KEEP_LABELS, SW_PCC = 1, 2, 4
 SW_MODE_PLAIN, SW_MODE_BATCHED = 0, 1
 JOB_STATES = {0: "queued", 1: "running", 2: "done", 3: "rejected", 4: "cancelled"}
-PHASES = ("k1_bond_label", "k2_merge_fliptab", "k3_flip", "pcc", "measure", "batched")
+PHASES = ("k1_bond_label", "k2_merge", "k3_flip", "pcc", "measure", "batched", "k3_resolve")
 
 
 class SwError(RuntimeError):
@@ -276,10 +276,11 @@ class Lattice:
         _check(lib().sw_set_timing(self._h, 1 if on else 0))
 
     def timing(self):
-        ms = (ctypes.c_double * 6)()
-        n = (ctypes.c_int64 * 6)()
-        _check(lib().sw_get_timing(self._h, ms, n, 6))
-        return {PHASES[k]: (float(ms[k]), int(n[k])) for k in range(6)}
+        k = len(PHASES)
+        ms = (ctypes.c_double * k)()
+        n = (ctypes.c_int64 * k)()
+        _check(lib().sw_get_timing(self._h, ms, n, k))
+        return {PHASES[i]: (float(ms[i]), int(n[i])) for i in range(k)}
 
 
 class Server:

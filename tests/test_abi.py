@@ -72,7 +72,7 @@ def test_tile_shapes_table(lib_path):
 
     for dim in (2, 3):
         shapes = swgpu.tile_shapes(dim)
-        assert len(shapes) >= 3
+        assert len(shapes) >= 2
         for tx, ty, tz in shapes:
-            assert tx % 16 == 0 and tx * ty * tz <= 32768
+            assert tx % 16 == 0 and tx * ty * tz <= 32768 and ty * tz == 64
             assert (tz == 1) == (dim == 2)

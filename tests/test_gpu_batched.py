@@ -1,8 +1,8 @@
-"""Batched persistent engine and PCC feedback against the oracle (GPU).
+"""Batched mode and PCC feedback against the oracle (GPU).
 
-Replicas of different dim, L, T, seeds and flags share one persistent launch
-(replayed from a hipGraph); each must follow exactly the trajectory the
-oracle computes for it alone.  PCC replicas must reproduce the oracle's
+Replicas of different dim, L, T, seeds and flags share every phase launch
+(the sweeps of a call replayed from one hipGraph); each must follow exactly
+the trajectory the oracle computes for it alone.  PCC replicas must reproduce the oracle's
 percolation flags and p values bit for bit.
 """
 import numpy as np
@@ -81,7 +81,7 @@ def test_batched_then_plain_then_batched():
 def test_batched_tile_shapes_and_grid_do_not_change_results():
     specs = MIX
     ref = [_oracle(s, 3) for s in specs]
-    for shape in range(3):
+    for shape in range(len(swgpu.tile_shapes(2))):
         with swgpu.Lattice([_params(s) for s in specs]) as lat:
             for r in range(len(specs)):
                 lat.set_tile_shape(r, shape)
