@@ -17,12 +17,13 @@ Extra objects on the JSON line:
   batched       (--batched) 512 uneven replicas: batched phase launches replayed from a hipGraph
                 vs plain per-lattice launches, site-updates/s each
 
-Usage: python bench.py [--gpus 1] [--steps 200] [--warmup 5] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps 200] [--warmup 20] [--no-cpu-baseline]
        [--batched] [--copy-probe]
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -39,10 +40,8 @@ HBM_PEAK_GBS = 8000.0
 ALGO_BYTES_PER_SITE = {
     "k1_bond_label": 3.0,     # read the int8 spin, write the 16-bit tile label
     "k3_flip": 3.0,           # read the 16-bit tile label, write the int8 spin
-    "k3_resolve": 0.25,       # read the border bitmap, write the border flip bits (1 bit each per site)
 }
-KERNEL_SYMBOLS = {"k1_bond_label": "k1_kernel", "k2_merge": "k2_kernel", "k3_flip": "k3_kernel",
-                  "k3_resolve": "k3a_kernel"}
+KERNEL_SYMBOLS = {"k1_bond_label": "k1_kernel", "k2_merge": "k2_kernel", "k3_flip": "k3_kernel"}
 SOURCES = ["paper_0808_2109_amd/csrc/sw_device.hpp", "paper_0808_2109_amd/csrc/sw_kernels.hip"]
 
 
@@ -92,11 +91,125 @@ def traffic_from_profile(kernel_key: str, launch_sites: int):
     return k.get("hbm_bytes_per_launch")
 
 
+PROFILE_LATTICES = {2: ("2d_L8192", 8192 * 8192), 3: ("3d_L256", 256 ** 3)}
+
+
+def _kernel_of(name: str):
+    """(kernel key, lattice tag, sites) of a plain-path kernel name in a rocprofv3 database."""
+    import re
+
+    for key, sym in KERNEL_SYMBOLS.items():
+        if f"sw::{sym}<" in name:
+            m = re.search(r"TileCfg<(\d)", name)
+            if m and int(m.group(1)) in PROFILE_LATTICES:
+                tag, sites = PROFILE_LATTICES[int(m.group(1))]
+                return key, tag, sites
+    return None
+
+
+def _db_rows(db_dir: str, query: str):
+    import glob
+    import sqlite3
+
+    dbs = sorted(glob.glob(os.path.join(db_dir, "**", "*_results.db"), recursive=True))
+    if not dbs:
+        raise SystemExit(f"no rocprofv3 database under {db_dir}")
+    con = sqlite3.connect(dbs[-1])
+    try:
+        return list(con.execute(query))
+    finally:
+        con.close()
+
+
+def summarize_profiles(prof_dir: str, out_dir: str, trace_cmd: str, pmc_cmd: str, copy_cmd: str):
+    """Kernel-trace statistics and HBM traffic per launch from rocprofv3 runs.
+
+    prof_dir holds the databases of five runs: trace/ (--kernel-trace --stats),
+    fetch/ and write/ (--pmc FETCH_SIZE, --pmc WRITE_SIZE on the same bench
+    command) and copy_fetch/, copy_write/ (the same counters on a plain device
+    copy of known size, which gives the scale of each counter).
+    """
+    import collections
+
+    os.makedirs(out_dir, exist_ok=True)
+    # 1) kernel trace: calls, mean / min / max duration per kernel
+    rows = _db_rows(os.path.join(prof_dir, "trace"), "select name, duration from kernels")
+    stats = collections.defaultdict(list)
+    for name, dur in rows:
+        stats[name].append(dur / 1e3)
+    total = sum(sum(v) for v in stats.values())
+    lines = [f"# rocprofv3 kernel trace, plain sweep workload (8192^2 at T_c + 256^3 at T=4.5115)",
+             f"# command: {trace_cmd}", "#",
+             f"# {'calls':>6} {'mean_us':>10} {'min_us':>10} {'max_us':>10} {'share':>7}  kernel"]
+    for name, v in sorted(stats.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"  {len(v):6d} {sum(v) / len(v):10.2f} {min(v):10.2f} {max(v):10.2f} "
+                     f"{100 * sum(v) / total:6.1f}%  {name[:110]}")
+    trace_means = {}
+    for name, v in stats.items():
+        k = _kernel_of(name)
+        if k:
+            trace_means[f"{k[0]}:{k[1]}"] = sum(v) / len(v)
+    with open(os.path.join(out_dir, "sweep_kernel_trace.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+    # 2) counters: KiB per dispatch summed over the counter's instances
+    def per_dispatch(sub: str, counter: str):
+        q = ("select k.dispatch_id, k.name, p.counter_value from pmc_events p join kernels k "
+             f"on p.dispatch_id = k.dispatch_id where p.counter_name = '{counter}'")
+        acc = collections.defaultdict(float)
+        names = {}
+        for did, name, val in _db_rows(os.path.join(prof_dir, sub), q):
+            acc[did] += val
+            names[did] = name
+        by = collections.defaultdict(list)
+        for did, v in acc.items():
+            by[names[did]].append(v)
+        return {n: sum(v) / len(v) for n, v in by.items()}
+
+    fetch, write = per_dispatch("fetch", "FETCH_SIZE"), per_dispatch("write", "WRITE_SIZE")
+    cf, cw = per_dispatch("copy_fetch", "FETCH_SIZE"), per_dispatch("copy_write", "WRITE_SIZE")
+    copy_kib = COPY_PROBE_BYTES / 1024.0
+    cname = [n for n in cf if "copyBuffer" in n or "copy" in n.lower()]
+    if not cname:
+        raise SystemExit("no copy kernel in the copy-probe databases")
+    fetch_scale = copy_kib / cf[cname[0]]
+    write_scale = copy_kib / cw[cname[0]]
+    kernels = {}
+    lines = [f"# HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (KiB per dispatch, summed over",
+             f"# instances), each scaled by what the counter reads for a device copy of {COPY_PROBE_BYTES} bytes",
+             f"# (FETCH_SIZE reads {cf[cname[0]]:.0f} KiB -> x{fetch_scale:.3f}; WRITE_SIZE reads {cw[cname[0]]:.0f} KiB "
+             f"-> x{write_scale:.3f})",
+             f"# commands: {pmc_cmd}", f"#           {copy_cmd}", "#",
+             f"# {'fetch_MB':>10} {'write_MB':>10} {'algo_MB':>10} {'traffic/algo':>12}  kernel"]
+    for name in sorted(fetch):
+        k = _kernel_of(name)
+        fb = fetch[name] * 1024 * fetch_scale
+        wb = write.get(name, 0.0) * 1024 * write_scale
+        algo = None
+        if k:
+            key, tag, sites = k
+            algo = ALGO_BYTES_PER_SITE.get(key, 0.0) * sites
+            kernels[f"{key}:{tag}"] = {"sites": sites, "hbm_bytes_per_launch": fb + wb, "fetch_bytes": fb,
+                                       "write_bytes": wb, "trace_mean_us": trace_means.get(f"{key}:{tag}")}
+        ratio = f"{(fb + wb) / algo:12.2f}" if algo else f"{'-':>12}"
+        lines.append(f"  {fb / 1e6:10.2f} {wb / 1e6:10.2f} {(algo or 0) / 1e6:10.2f} {ratio}  {name[:100]}")
+    with open(os.path.join(out_dir, "sweep_hbm_traffic.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    with open(os.path.join(out_dir, "traffic_pmc.json"), "w") as f:
+        json.dump({"source_hash": source_hash(), "fetch_scale": fetch_scale, "write_scale": write_scale,
+                   "kernels": kernels}, f, indent=1)
+    print(json.dumps({"written": [os.path.join(out_dir, n) for n in
+                                  ("sweep_kernel_trace.txt", "sweep_hbm_traffic.txt", "traffic_pmc.json")]}))
+
+
+COPY_PROBE_BYTES = 256 << 20
+
+
 def copy_probe():
     """A plain device copy of known size, for scaling the FETCH/WRITE counters."""
     import torch
 
-    n = 256 << 20
+    n = COPY_PROBE_BYTES
     src = torch.ones(n, dtype=torch.int8, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(5):
@@ -113,8 +226,9 @@ def run_batched(swgpu, workloads, sweeps_batched: int, sweeps_plain: int):
     sites = sum(r.nsites for r in wl.replicas)
     out = {"replicas": len(params), "sites": sites}
     with swgpu.Lattice(params) as lat:
-        lat.autotune(sweeps=2)
         lat.set_mode(swgpu.SW_MODE_BATCHED)
+        lat.sweep(10)                       # warm-up: the tuner times the current state
+        lat.autotune(sweeps=2)
         lat.sweep(1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -139,13 +253,20 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--batched", action="store_true", help="also time the 512-replica batched workload")
-    ap.add_argument("--batched-sweeps", type=int, default=100)
+    ap.add_argument("--batched-sweeps", type=int, default=500)
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--summarize", metavar="PROF_DIR",
+                    help="write the profiles/ summaries from rocprofv3 runs under PROF_DIR (no GPU needed)")
+    ap.add_argument("--summary-commands", nargs=3, metavar=("TRACE", "PMC", "COPY"), default=("?", "?", "?"))
     args = ap.parse_args()
+
+    if args.summarize:
+        summarize_profiles(args.summarize, os.path.join(ROOT, "profiles"), *args.summary_commands)
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -162,18 +283,23 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     wl = workloads.plain()
-    lats = []
-    for rep in wl.replicas:
-        lat = swgpu.Lattice(swgpu.params_from_replica(rep))
-        if not args.no_autotune:
-            lat.autotune(sweeps=3)
-        lats.append(lat)
-    shapes = [swgpu.tile_shapes(r.dim)[lat.tile_shape(0)] for r, lat in zip(wl.replicas, lats)]
+    # one stream for both lattices: their sweeps run one after the other, so
+    # every kernel's event-timed duration is its own, not shared with the other
+    # lattice's kernels
+    stream = torch.cuda.Stream()
+    handle = ctypes.c_void_p(stream.cuda_stream)
+    lats = [swgpu.Lattice(swgpu.params_from_replica(rep), stream=handle) for rep in wl.replicas]
     log(f"workload {wl.name}: {[r.nsites for r in wl.replicas]} sites, warmup {args.warmup}, steps {args.steps}")
-
+    # warm up first: the autotuner times the tile shapes on a copy of the
+    # current (equilibrated) state
     for _ in range(args.warmup):
         for lat in lats:
             lat.sweep(1)
+    torch.cuda.synchronize()
+    if not args.no_autotune:
+        for lat in lats:
+            lat.autotune(sweeps=3)
+    shapes = [swgpu.tile_shapes(r.dim)[lat.tile_shape(0)] for r, lat in zip(wl.replicas, lats)]
     torch.cuda.synchronize()
     for lat in lats:
         lat.set_timing(True)

@@ -3,10 +3,10 @@
 // Results never depend on the tile shape or the grid (every union hooks to
 // the smaller root), so the tuner is free to pick whatever runs fastest.
 //   one replica:   every compiled tile shape is timed with plain launches on
-//                  a scratch lattice with the same parameters;
+//                  a scratch lattice with the same parameters and state;
 //   many replicas: every batched variant (a 2D and a 3D shape) and three
-//                  grid sizes are timed on a scratch copy of all
-//                  replicas in batched mode.
+//                  grid sizes are timed on a scratch copy of all replicas
+//                  (parameters and state) in batched mode.
 // Choices are cached as JSON keyed by (arch, dim, size class = floor(log2 L))
 // for single lattices and by (arch, "batch", replica count, total sites) for
 // batches.
@@ -80,6 +80,21 @@ static void write_cache(const char* path, const std::map<std::string, Choice>& e
     fclose(f);
 }
 
+// scratch replica r of s starts from the current spins and sweep counter of
+// replica src of h (cluster sizes, and so the cost of a sweep, depend on the
+// state: a random start is not representative)
+static int copy_state(sw_lattice* s, int r, const sw_lattice* h, int src)
+{
+    const SwRep& from = h->reps[src].h;
+    SwRep& to = s->reps[r].h;
+    hipError_t e = hipMemcpyAsync(to.spins, from.spins, from.N, hipMemcpyDeviceToDevice, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "copying spins to the tuning lattice");
+    to.sweep = from.sweep;
+    to.thr = from.thr;
+    to.p = from.p;
+    return push_desc(s, r);
+}
+
 // milliseconds per sweep of `sweeps` sweeps on handle s (after one untimed sweep)
 static int time_sweeps(sw_lattice* s, int sweeps, double* ms_out)
 {
@@ -120,6 +135,7 @@ static int tune_single(sw_lattice* h, int32_t sweeps, const char* cache_path)
         sw_lattice* s = nullptr;
         int rc = sw_init(&p, 1, -1, h->stream, &s);
         if (!rc) rc = sw_set_tile_shape(s, 0, shape);
+        if (!rc) rc = copy_state(s, 0, h, 0);
         double ms = 0;
         if (!rc) rc = time_sweeps(s, sweeps, &ms);
         if (s) sw_free(s);
@@ -159,6 +175,7 @@ static int tune_batch(sw_lattice* h, int32_t sweeps, const char* cache_path)
             sw_lattice* s = nullptr;
             int rc = sw_init(ps.data(), (int32_t)ps.size(), -1, h->stream, &s);
             for (size_t r = 0; r < ps.size() && !rc; ++r) rc = sw_set_tile_shape(s, (int32_t)r, v);
+            for (size_t r = 0; r < ps.size() && !rc; ++r) rc = copy_state(s, (int)r, h, (int)r);
             if (!rc) s->mode = SW_MODE_BATCHED;
             for (int per_cu : {4, 8, 16}) {
                 if (rc) break;

@@ -14,10 +14,10 @@
 //       the two ends of every open link that leaves a tile (the border
 //       reconciliation of Sec. II, in one pass instead of the master's second
 //       labelling or the iterated neighbour exchange).
-//   K3a per border root: find its cluster root (the smallest site index of the
-//       cluster: the label identity that the min-label rule of Sec. II.B
-//       converges to) and that cluster's flip bit.
-//   K3b per tile: give every site its cluster's new spin (Sec. I step 3).
+//   K3  per tile: find the cluster root of each of the tile's border roots
+//       (the smallest site index of the cluster: the label identity that the
+//       min-label rule of Sec. II.B converges to) and give every site its
+//       cluster's new spin (Sec. I step 3).
 // plus the extension-rule percolation test and p feedback of Sec. III.
 //
 // Every union hooks the larger root under the smaller one, so the final roots
@@ -32,7 +32,6 @@ namespace sw {
 
 constexpr int kBlock = 256;            // threads per workgroup (4 wave64)
 constexpr uint32_t kTagInit = 0, kTagBond = 1, kTagRefine = 2, kTagFlip = 3;
-constexpr uint32_t kBorderFlag = 0x8000u;
 
 enum : uint32_t { FLAG_SERIES = 1u, FLAG_KEEP = 2u, FLAG_PCC = 4u };
 
@@ -62,12 +61,11 @@ struct SwRep {
     int32_t active;             // batched mode: replica takes part
     int32_t pad0;
     int8_t* spins;              // N
-    uint16_t* lab16;            // N tile-local labels | border flag
+    uint16_t* lab16;            // N tile-local labels (tile-local index of the cluster's tile root)
     int32_t* par;               // N global union-find parents (border roots only)
     int32_t* lab32;             // N final labels (FLAG_KEEP or FLAG_PCC), else null
     uint32_t* xbits;            // ntiles * xwords crossing-link bits
     uint32_t* fbits;            // ntiles * fbw: border roots of each tile (bit per tile-local site)
-    uint32_t* bflip;            // ntiles * fbw: flip bits of those border roots
     uint16_t* face;             // ntiles * 2 * ft: labels of the near, then the far face sites
     int64_t* series;            // 2 * series_cap
     int64_t* acc;               // 2 scratch accumulators (measure)
@@ -144,7 +142,7 @@ struct TileCfg {
     static_assert(TX == 32 || TX == 64, "a wave64 covers whole tile rows");
     static_assert(TS % kBlock == 0, "whole sites per thread");
     static_assert(NR <= kBlock, "one thread per row for the halo column");
-    static_assert(TS <= 32768, "tile-local labels are 15-bit");
+    static_assert(TS <= 65536, "tile-local labels are 16-bit");
 };
 
 struct TileGeo {
@@ -188,7 +186,7 @@ __device__ __forceinline__ uint32_t tile_root_of(const SwRep& R, uint32_t gi, ui
     const int x0 = (int)(x / C::TX) * C::TX;
     const int y0 = (int)(y / C::TY) * C::TY;
     const int z0 = (C::D == 3) ? (int)(z / C::TZ) * C::TZ : 0;
-    const uint32_t lr = v & 0x7FFFu;
+    const uint32_t lr = v;
     const uint32_t r = (lr < (uint32_t)C::TS) ? local_to_global<C>(lr, x0, y0, z0, (int)L) : 0xFFFFFFFFu;
     if (r > gi) {            // a tile root precedes every site of its cluster
         flag_error(R, ERR_TILE_LABEL);
@@ -203,7 +201,9 @@ __device__ __forceinline__ uint64_t low_bits(int n) { return n >= 64 ? ~0ull : (
 // Union-find primitives.  Parents only ever point to smaller indices of the
 // same cluster, so the root of a cluster is its smallest member.  A find may
 // shorten paths with plain stores (every store writes an ancestor); a union
-// hooks with an atomic min and retries from the value it displaced.
+// hooks with an atomic min and retries from the value it displaced.  In LDS
+// (the tile labelling) the two chains of a union are walked together and its
+// ends are then pointed at the joint root.
 // --------------------------------------------------------------------------
 __device__ __forceinline__ int lds_load(const int* p)
 {
@@ -213,18 +213,6 @@ __device__ __forceinline__ int lds_load(const int* p)
 __device__ __forceinline__ void lds_store(int* p, int v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-__device__ __forceinline__ int lds_find(int* par, int x)
-{
-    while (true) {
-        const int p = lds_load(&par[x]);
-        if (p == x) return x;
-        const int gp = lds_load(&par[p]);
-        if (gp == p) return p;
-        lds_store(&par[x], gp);
-        x = gp;
-    }
 }
 
 // root of x without writing: safe while other threads replace parents by
@@ -237,23 +225,6 @@ __device__ __forceinline__ int lds_root(const int* par, int x)
         p = lds_load(&par[x]);
     }
     return x;
-}
-
-__device__ __forceinline__ void lds_unite(int* par, int a, int b)
-{
-    while (true) {
-        a = lds_find(par, a);
-        b = lds_find(par, b);
-        if (a == b) return;
-        if (a > b) {
-            const int t = a;
-            a = b;
-            b = t;
-        }
-        const int old = atomicMin(&par[b], a);
-        if (old == b) return;
-        b = old;
-    }
 }
 
 // Union of the sets of a and b for the tile labelling: both chains are walked
@@ -437,6 +408,8 @@ __device__ __forceinline__ uint64_t row_flips(uint32_t gb, int wx, uint32_t s, u
 // overlapping runs that share an open bond, made by the thread whose part
 // holds the first such bond.
 // --------------------------------------------------------------------------
+constexpr int kRing = 128;   // per-wave union queue entries (a power of two, >= 2 x 64)
+
 template <class C>
 struct K1Cfg {
     static constexpr int RQ = C::TX / 16;      // threads per row
@@ -451,6 +424,7 @@ struct alignas(16) K1Smem {
     uint64_t S[C::NR];     // spin-up masks of the rows
     uint64_t SS[C::NR];    // run starts of the rows
     uint32_t XF[2];        // open links leaving through the far x face (bit = row)
+    uint32_t ring[kBlock / 64][kRing];   // per-wave queue of pending unions
 };
 
 // spins of 4 / 16 sites -> their up bits (a spin is up when it is positive)
@@ -630,76 +604,84 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
 
     // 3) unions between runs of neighbouring rows.  Within a stretch where
     //    neither row starts a new run both rows stay in the same two runs, so
-    //    only the first open bond of each stretch is joined.
+    //    only the first open bond of each stretch is joined.  Each wave queues
+    //    its unions and runs them 64 at a time, so the time goes with the
+    //    wave's number of unions rather than with its busiest thread.
+    {
+        const int lane = tid & 63, wave = tid >> 6;
+        uint32_t* ring = sm.ring[wave];
+        uint32_t tail = 0, head = 0;
 #pragma unroll
-    for (int dd = 1; dd < C::D; ++dd) {
-        const int step = (dd == 1) ? 1 : C::TY;
-        const bool inner = rowok && ((dd == 1) ? (ly < g.wy - 1) : (lz < g.wz - 1));
-        if (!inner) continue;
-        const uint64_t SSp = sm.SS[r + step];
-        const uint64_t V = opn[dd];
-        const uint64_t Mc = ~(SS | SSp);                 // neither row starts a run here
-        const uint64_t A = V | Mc;
-        const uint64_t carry = (A + V) ^ A ^ V;          // an open bond earlier in the stretch
-        uint64_t U = V & ~(Mc & carry) & (0xFFFFull << xp);
-        while (U) {
-            const int x = __builtin_ctzll(U);
-            U &= U - 1ull;
-            lds_join(sm.par, r * C::TX + start_at(SS, x), (r + step) * C::TX + start_at(SSp, x));
+        for (int dd = 1; dd < C::D; ++dd) {
+            const int step = (dd == 1) ? 1 : C::TY;
+            const bool inner = rowok && ((dd == 1) ? (ly < g.wy - 1) : (lz < g.wz - 1));
+            uint64_t U = 0, SSp = 0;
+            if (inner) {
+                SSp = sm.SS[r + step];
+                const uint64_t V = opn[dd];
+                const uint64_t Mc = ~(SS | SSp);                 // neither row starts a run here
+                const uint64_t A = V | Mc;
+                const uint64_t carry = (A + V) ^ A ^ V;          // an open bond earlier in the stretch
+                U = V & ~(Mc & carry) & (0xFFFFull << xp);
+            }
+            while (__ballot(U != 0ull)) {
+                const bool want = U != 0ull;
+                uint32_t pr = 0;
+                if (want) {
+                    const int x = __builtin_ctzll(U);
+                    U &= U - 1ull;
+                    pr = (uint32_t)(r * C::TX + start_at(SS, x)) | ((uint32_t)((r + step) * C::TX + start_at(SSp, x)) << 16);
+                }
+                const uint64_t bal = __ballot(want);
+                if (want) ring[(tail + (uint32_t)lanes_below(bal)) & (kRing - 1)] = pr;
+                tail += (uint32_t)__popcll(bal);
+                if (tail - head >= 64u) {
+                    wave_lds_sync();
+                    const uint32_t e = ring[(head + (uint32_t)lane) & (kRing - 1)];
+                    lds_join(sm.par, (int)(e & 0xFFFFu), (int)(e >> 16));
+                    head += 64u;
+                    wave_lds_sync();
+                }
+            }
+        }
+        wave_lds_sync();
+        if ((uint32_t)lane < tail - head) {
+            const uint32_t e = ring[(head + (uint32_t)lane) & (kRing - 1)];
+            lds_join(sm.par, (int)(e & 0xFFFFu), (int)(e >> 16));
         }
     }
     __syncthreads();
 
-    // 4) compress (one store per run start, of its root: the read-only walk is
-    //    safe against the other threads' stores) and border flags: a cluster
-    //    is a border cluster when one of its runs touches a near face or has
-    //    an open link leaving through a far face
+    // 4) tile-local labels (the cluster's tile root) of the part and of its
+    //    face sites, and border flags: a cluster is a border cluster when one
+    //    of its runs touches a near face or has an open link leaving through a
+    //    far face.  Every run start walks to its root once (read only: the
+    //    parents no longer change).
     if (partok) {
+        uint16_t* nearf = R.face + (size_t)t * (2 * C::FT);
+        uint16_t* farf = nearf + C::FT;
+        const int rowk = r * C::TX;
         const bool nearrow = ly == 0 || (C::D == 3 && lz == 0);
         uint64_t cross = 0;                                   // open links leaving through the far y / z faces
         if (edgeY) cross |= opn[1];
         if (edgeZ) cross |= opn[C::D - 1];
         const int last = 63 - __clzll((long long)SS);
         const bool xout = (opn[0] >> (g.wx - 1)) & 1ull;
-        uint64_t st = SS & (0xFFFFull << xp);
-        while (st) {
-            const int x = __builtin_ctzll(st);
-            st &= st - 1ull;
-            const int k = r * C::TX + x;
-            const int root = lds_root(sm.par, k);
-            lds_store(&sm.par[k], root);
-            bool b = nearrow || x == 0 || (x == last && xout);
-            if (!b && cross) {
-                const uint64_t later = SS & ~low_bits(x + 1);
-                const int xe = later ? __builtin_ctzll(later) - 1 : g.wx - 1;   // last site of the run
-                b = (cross & low_bits(xe + 1) & ~low_bits(x)) != 0ull;
-            }
-            if (b) atomicOr(&sm.FB[root >> 5], 1u << (root & 31));
-        }
-    }
-    __syncthreads();
-
-    // 5) tile-local labels (root | border flag) of the part and of its face
-    //    sites; border roots start their own global tree; the border bitmap
-    //    and the far x face's crossing bits
-    for (int w = tid; w < C::FBW; w += blockDim.x) R.fbits[(size_t)t * C::FBW + w] = sm.FB[w];
-    if (tid < C::W0) R.xbits[(size_t)t * C::XW + tid] = sm.XF[tid];
-    if (partok) {
-        uint16_t* nearf = R.face + (size_t)t * (2 * C::FT);
-        uint16_t* farf = nearf + C::FT;
-        const int rowk = r * C::TX;
-        auto label = [&](int x) {
-            const int root = sm.par[rowk + start_at(SS, x)];
-            return (uint32_t)root | (((sm.FB[root >> 5] >> (root & 31)) & 1u) << 15);
-        };
-        uint32_t cur = label(xp);
+        uint32_t cur = (uint32_t)lds_root(sm.par, rowk + start_at(SS, xp));
         uint32_t pk[8];
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int x = xp + j;
-            if (j > 0 && x < g.wx && ((SS >> x) & 1ull)) cur = label(x);
-            if (x < g.wx && ((SS >> x) & 1ull) && (cur & 0x7FFFu) == (uint32_t)(rowk + x) && (cur & kBorderFlag))
-                R.par[gi0 + (uint32_t)x] = (int32_t)(gi0 + (uint32_t)x);
+            if (x < g.wx && ((SS >> x) & 1ull)) {
+                if (j > 0) cur = (uint32_t)lds_root(sm.par, rowk + x);
+                bool b = nearrow || x == 0 || (x == last && xout);
+                if (!b && cross) {
+                    const uint64_t later = SS & ~low_bits(x + 1);
+                    const int xe = later ? __builtin_ctzll(later) - 1 : g.wx - 1;   // last site of the run
+                    b = (cross & low_bits(xe + 1) & ~low_bits(x)) != 0ull;
+                }
+                if (b) atomicOr(&sm.FB[cur >> 5], 1u << (cur & 31u));
+            }
             if (j & 1) pk[j >> 1] |= cur << 16;
             else pk[j >> 1] = cur;
         }
@@ -725,9 +707,27 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
                 if (edgeZ) farf[zfi + j] = v;
             }
         }
-        if (q == 0) nearf[r] = (uint16_t)label(0);                     // x faces: index ly + TY*lz
-        if (xp <= g.wx - 1 && g.wx - 1 < xp + 16) farf[r] = (uint16_t)label(g.wx - 1);
+        if (q == 0) nearf[r] = (uint16_t)pk[0];                              // x faces: index ly + TY*lz
+        if (xp <= g.wx - 1 && g.wx - 1 < xp + 16) {
+            const int jl = g.wx - 1 - xp;
+            farf[r] = (uint16_t)(pk[jl >> 1] >> (16 * (jl & 1)));
+        }
     }
+    __syncthreads();
+
+    // 5) the border bitmap and the far x face's crossing bits; every border
+    //    root starts its own tree in the global union-find
+    for (int w = tid; w < C::FBW; w += blockDim.x) {
+        uint32_t m = sm.FB[w];
+        R.fbits[(size_t)t * C::FBW + w] = m;
+        while (m) {
+            const int b = __ffs(m) - 1;
+            m &= m - 1u;
+            const uint32_t gi = local_to_global<C>((uint32_t)(w * 32 + b), g.x0, g.y0, g.z0, (int)L);
+            R.par[gi] = (int32_t)gi;
+        }
+    }
+    if (tid < C::W0) R.xbits[(size_t)t * C::XW + tid] = sm.XF[tid];
     __syncthreads();
 }
 
@@ -776,12 +776,12 @@ __device__ void k2_link(const SwRep& R, int t, int f)
     if (first > 0 && ((xb[wbase + ((fb - 1) >> 5)] >> ((fb - 1) & 31)) & 1u) && farf[f - 1] == la &&
         nearf[f - 1] == lb)
         return;
-    if (!(la & lb & kBorderFlag)) {                 // both ends are border roots' sites
+    if (la >= (uint32_t)C::TS || lb >= (uint32_t)C::TS) {
         flag_error(R, ERR_TILE_LABEL);
         return;
     }
-    const uint32_t ra = tile_site_global<C>(R, ix, iy, iz, la & 0x7FFFu);
-    const uint32_t rb = tile_site_global<C>(R, jx, jy, jz, lb & 0x7FFFu);
+    const uint32_t ra = tile_site_global<C>(R, ix, iy, iz, la);
+    const uint32_t rb = tile_site_global<C>(R, jx, jy, jz, lb);
     if (ra >= R.N || rb >= R.N) {
         flag_error(R, ERR_TILE_LABEL);
         return;
@@ -790,45 +790,21 @@ __device__ void k2_link(const SwRep& R, int t, int f)
 }
 
 // --------------------------------------------------------------------------
-// K3a: border roots.  Word w of tile t's border bitmap lists 32 tile-local
-// sites; each border root among them finds its cluster root (the smallest
-// site index of the cluster), takes it as parent, and the cluster's flip bit
-// is recorded for the flip pass.
-// --------------------------------------------------------------------------
-template <class C>
-__device__ void k3a_word(const SwRep& R, int t, int w, uint32_t s)
-{
-    uint32_t m = R.fbits[(size_t)t * C::FBW + w];
-    uint32_t out = 0;
-    if (m) {
-        const int ix = t % R.ntx, iy = (t / R.ntx) % R.nty, iz = t / (R.ntx * R.nty);
-        const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
-        while (m) {
-            const int b = __ffs(m) - 1;
-            m &= m - 1u;
-            const uint32_t gi = tile_site_global<C>(R, ix, iy, iz, (uint32_t)(w * 32 + b));
-            if (gi >= R.N) {
-                flag_error(R, ERR_TILE_LABEL);
-                continue;
-            }
-            const uint32_t root = ro_find(R, gi);
-            if (root != gi) R.par[gi] = (int32_t)root;
-            out |= flip_bit(root, s, k0, k1) << b;
-        }
-    }
-    R.bflip[(size_t)t * C::FBW + w] = out;
-}
-
-// --------------------------------------------------------------------------
-// K3b: cluster flip.  A site's tile-local root is either interior (its own
-// index is the cluster label, its flip bit comes from the tile's own row of
-// flip bits) or a border root (flip bit from K3a).  Optionally writes the
-// final labels and marks percolation coverage (PCC).
+// K3: cluster flip.  The tile's border roots (its border bitmap) find their
+// cluster roots, the smallest site index of the cluster (the label identity
+// that the min-label rule of Sec. II.B converges to), and that cluster's flip
+// bit; an interior root is its own cluster label and takes its flip bit from
+// the tile's own rows of flip bits.  Every site then gets its cluster's new
+// spin.  Optionally writes the final labels and marks percolation coverage
+// (PCC).
 // --------------------------------------------------------------------------
 template <class C>
 struct K3Smem {
-    uint64_t RF[C::NR];     // flip bits of the tile's own sites, one mask per row
-    uint32_t BF[C::FBW];    // flip bits of the tile's border roots
+    uint64_t RF[C::NR];          // flip bits of the tile's own sites, one mask per row
+    uint32_t BF[C::FBW];         // flip bits of the tile's border roots
+    uint32_t FBt[C::FBW];        // the tile's border-root bitmap
+    uint16_t list[2 * C::FT];    // the tile's border roots (each has a site on a face)
+    int cnt;
 };
 
 template <class C>
@@ -856,16 +832,16 @@ __device__ __forceinline__ uint32_t k3_site(const SwRep& R, const K3Smem<C>& sm,
                                             uint32_t gi, bool labels, bool pcc, uint64_t tag, uint32_t bw,
                                             uint32_t nslots)
 {
-    const uint32_t lr = v & 0x7FFFu;
+    const uint32_t lr = v;
     if (lr > (uint32_t)k) {                 // a tile root precedes its sites
         flag_error(R, ERR_TILE_LABEL);
         return 0xFFu;
     }
-    const bool border = (v & kBorderFlag) != 0;
+    const bool border = (sm.FBt[lr >> 5] >> (lr & 31u)) & 1u;
     const uint32_t bit = border ? (sm.BF[lr >> 5] >> (lr & 31u)) & 1u : (uint32_t)(sm.RF[lr / C::TX] >> (lr % C::TX)) & 1u;
     if (labels || pcc) {
         uint32_t root = local_to_global<C>(lr, g.x0, g.y0, g.z0, R.L);
-        if (border) root = (uint32_t)R.par[root];   // K3a made it the cluster root
+        if (border) root = (uint32_t)R.par[root];   // set to the cluster root above
         if (root >= R.N) {
             flag_error(R, ERR_PARENT);
             root = 0;
@@ -887,29 +863,82 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
     const TileGeo g = tile_geo<C>(R, t);
     const uint32_t L = (uint32_t)R.L;
     const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
-    if (tid < C::NR) {
-        const int ly = tid % C::TY, lz = tid / C::TY;
-        uint64_t m = 0;
-        if (ly < g.wy && lz < g.wz)
-            m = row_flips((uint32_t)g.x0 + L * ((uint32_t)(g.y0 + ly) + L * (uint32_t)(g.z0 + lz)), g.wx, s, k0, k1);
-        sm.RF[tid] = m;
-    }
-    for (int w = tid; w < C::FBW; w += kBlock) sm.BF[w] = R.bflip[(size_t)t * C::FBW + w];
-    __syncthreads();
     const bool labels = R.lab32 != nullptr;
     const bool pcc = (R.flags & FLAG_PCC) != 0;
+    constexpr int CAP = 2 * C::FT;
+    constexpr int QR = C::TX / 4;                       // quads of sites per row
+    constexpr int QPT = C::TS / 4 / kBlock;             // quads per thread (blockDim = kBlock)
+    const bool quads = (L & 3u) == 0;                   // then every row and the tile width are multiples of 4
+
+    // 0) the tile's labels, four sites per thread and load, issued first so
+    //    that they arrive while the border roots are resolved
+    uint2 lv[QPT];
+#pragma unroll
+    for (int j = 0; j < QPT; ++j) {
+        const int qd = tid + kBlock * j;
+        const int r = qd / QR, xq = (qd % QR) * 4;
+        const int ly = r % C::TY, lz = r / C::TY;
+        lv[j] = make_uint2(0u, 0u);
+        if (quads && ly < g.wy && lz < g.wz && xq < g.wx)
+            lv[j] = *reinterpret_cast<const uint2*>(R.lab16 + (uint32_t)(g.x0 + xq) +
+                                                    L * ((uint32_t)(g.y0 + ly) + L * (uint32_t)(g.z0 + lz)));
+    }
+
+    // 1) the tile's border roots into a list; the flip bits of its own rows
+    if (tid == 0) sm.cnt = 0;
+    for (int w = tid; w < C::FBW; w += blockDim.x) sm.BF[w] = 0;
+    __syncthreads();
+    for (int w = tid; w < C::FBW; w += blockDim.x) {
+        uint32_t m = R.fbits[(size_t)t * C::FBW + w];
+        sm.FBt[w] = m;
+        if (!m) continue;
+        int pos = atomicAdd(&sm.cnt, __popc(m));
+        while (m) {
+            const int b = __ffs(m) - 1;
+            m &= m - 1u;
+            if (pos < CAP) sm.list[pos] = (uint16_t)(w * 32 + b);
+            ++pos;
+        }
+    }
+    if (tid < C::NR) {
+        const int ly = tid % C::TY, lz = tid / C::TY;
+        uint64_t rf = 0;
+        if (ly < g.wy && lz < g.wz)
+            rf = row_flips((uint32_t)g.x0 + L * ((uint32_t)(g.y0 + ly) + L * (uint32_t)(g.z0 + lz)), g.wx, s, k0, k1);
+        sm.RF[tid] = rf;
+    }
+    __syncthreads();
+
+    // 2) border roots: cluster root (kept as parent when labels are written)
+    //    and the cluster's flip bit
+    const int nb = sm.cnt;
+    if (nb > CAP && tid == 0) flag_error(R, ERR_TILE_LABEL);   // more border roots than face sites
+    for (int i = tid; i < min(nb, CAP); i += blockDim.x) {
+        const uint32_t lr = sm.list[i];
+        const uint32_t gi = local_to_global<C>(lr, g.x0, g.y0, g.z0, (int)L);
+        if (gi >= R.N) {
+            flag_error(R, ERR_TILE_LABEL);
+            continue;
+        }
+        const uint32_t root = ro_find(R, gi);
+        if ((labels || pcc) && root != gi) R.par[gi] = (int32_t)root;
+        if (flip_bit(root, s, k0, k1)) atomicOr(&sm.BF[lr >> 5], 1u << (lr & 31u));
+    }
+    __syncthreads();
+
+    // 3) new spins
     const uint64_t tag = (uint64_t)(s + 1u) << 32;
     const uint32_t bw = (L + 31u) / 32u;               // bitmap words per candidate
     const uint32_t nslots = (C::D == 3) ? L * L : L;   // candidates per axis
-    if ((L & 3u) == 0) {
-        // four sites per thread: every row and the tile width are multiples of 4
-        constexpr int QR = C::TX / 4;
-        for (int qd = tid; qd < C::TS / 4; qd += kBlock) {
+    if (quads) {
+#pragma unroll
+        for (int j = 0; j < QPT; ++j) {
+            const int qd = tid + kBlock * j;
             const int r = qd / QR, xq = (qd % QR) * 4;
             const int ly = r % C::TY, lz = r / C::TY;
             if (ly >= g.wy || lz >= g.wz || xq >= g.wx) continue;
             const uint32_t gi = (uint32_t)(g.x0 + xq) + L * ((uint32_t)(g.y0 + ly) + L * (uint32_t)(g.z0 + lz));
-            const uint2 v = *reinterpret_cast<const uint2*>(R.lab16 + gi);
+            const uint2 v = lv[j];
             const int k = r * C::TX + xq;
             uint32_t out = k3_site<C>(R, sm, g, v.x & 0xFFFFu, k, gi, labels, pcc, tag, bw, nslots);
             out |= k3_site<C>(R, sm, g, v.x >> 16, k + 1, gi + 1, labels, pcc, tag, bw, nslots) << 8;
@@ -918,7 +947,7 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
             *reinterpret_cast<uint32_t*>(R.spins + gi) = out;
         }
     } else {
-        for (int k = tid; k < C::TS; k += kBlock) {
+        for (int k = tid; k < C::TS; k += blockDim.x) {
             const int xk = k % C::TX, r = k / C::TX;
             const int ly = r % C::TY, lz = r / C::TY;
             if (ly >= g.wy || lz >= g.wz || xk >= g.wx) continue;
@@ -962,7 +991,7 @@ __device__ void k_cand_tile(const SwRep& R, int t, uint32_t s)
             const uint32_t v = R.lab16[gi];
             uint32_t r = tile_root_of<C>(R, gi, v);
             if (r == 0xFFFFFFFFu) continue;
-            if (v & kBorderFlag) r = ro_find(R, r);
+            if ((R.fbits[(size_t)t * C::FBW + (v >> 5)] >> (v & 31u)) & 1u) r = ro_find(R, r);
             // in-plane position
             uint32_t slot;
             if (C::D == 2) slot = (a == 0) ? (uint32_t)y : (uint32_t)x;

@@ -1,11 +1,10 @@
 // sw_kernels.hip -- the HIP kernels of the sweep and their host launchers.
 //
-// Plain path: one launch per phase and replica (K1, K2, K3a, K3b, and for
-// PCC the candidate, coverage and feedback kernels).  K1 and K3b are grids of
-// workgroups that walk contiguous chunks of tiles; K2 and K3a run one thread
-// per face site / bitmap word of every tile.  Batched path: each phase is one
-// launch over the tiles of all replicas, and the launches of many sweeps are
-// replayed from one hipGraph.
+// Plain path: one launch per phase and replica (K1, K2, K3, and for PCC the
+// candidate, coverage and feedback kernels).  K1 and K3 run one workgroup per
+// tile, K2 one thread per far-face site of every tile.  Batched path: each
+// phase is one launch over the tiles of all replicas, and the launches of
+// many sweeps are replayed from one hipGraph.
 #include "sw_device.hpp"
 #include "sw_internal.hpp"
 
@@ -104,23 +103,13 @@ __global__ __launch_bounds__(kBlock) void k2_kernel(const SwRep* Rd)
     k2_link<C>(R, (int)(gid / C::FT), (int)(gid % C::FT));
 }
 
-template <class C>
-__global__ __launch_bounds__(kBlock) void k3a_kernel(const SwRep* Rd, uint32_t s)
-{
-    const SwRep R = *Rd;
-    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (gid >= (int64_t)R.ntiles * C::FBW) return;
-    k3a_word<C>(R, (int)(gid / C::FBW), (int)(gid % C::FBW), s);
-}
-
+// K3: one workgroup per tile, grid = ntiles (XCD-aware order)
 template <class C>
 __global__ __launch_bounds__(kBlock) void k3_kernel(const SwRep* Rd, uint32_t s)
 {
     __shared__ K3Smem<C> sm;
     const SwRep R = *Rd;
-    int t0, t1;
-    chunk_of(R.ntiles, t0, t1);
-    for (int t = t0; t < t1; ++t) k3_tile<C>(R, t, s, sm);
+    k3_tile<C>(R, xcd_item(R.ntiles), s, sm);
 }
 
 template <class C>
@@ -308,7 +297,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
     if (dst) wave_flush_em(e, m, dst);
 }
 
-// K2 and K3a: one workgroup per work item (launched with grid = nitems)
+// K2: one workgroup per work item (launched with grid = nitems)
 template <class C2, class C3>
 __global__ __launch_bounds__(kBlock) void kb2_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
                                                      int n_sweeps)
@@ -322,21 +311,6 @@ __global__ __launch_bounds__(kBlock) void kb2_kernel(SwRep* reps, const EngineIt
         for (int f = threadIdx.x; f < C2::FT; f += kBlock) k2_link<C2>(R, items[i].tile, f);
     else
         for (int f = threadIdx.x; f < C3::FT; f += kBlock) k2_link<C3>(R, items[i].tile, f);
-}
-
-template <class C2, class C3>
-__global__ __launch_bounds__(kBlock) void kb3a_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
-                                                      int n_sweeps)
-{
-    const int i = blockIdx.x;
-    if (i >= nitems) return;
-    const SwRep& R = reps[items[i].rep];
-    uint32_t s;
-    if (!rep_runs(R, it, n_sweeps, s)) return;
-    if (R.dim == 2)
-        for (int w = threadIdx.x; w < C2::FBW; w += kBlock) k3a_word<C2>(R, items[i].tile, w, s);
-    else
-        for (int w = threadIdx.x; w < C3::FBW; w += kBlock) k3a_word<C3>(R, items[i].tile, w, s);
 }
 
 template <class C2, class C3>
@@ -359,15 +333,12 @@ __global__ __launch_bounds__(kBlock) void kb3_kernel(SwRep* reps, const EngineIt
                                                      int n_sweeps)
 {
     __shared__ __align__(16) char smem[cmax2(sizeof(K3Smem<C2>), sizeof(K3Smem<C3>))];
-    int i0, i1;
-    chunk_of(nitems, i0, i1);
-    for (int i = i0; i < i1; ++i) {
-        const SwRep& R = reps[items[i].rep];
-        uint32_t s;
-        if (!rep_runs(R, it, n_sweeps, s)) continue;
-        if (R.dim == 2) k3_tile<C2>(R, items[i].tile, s, *reinterpret_cast<K3Smem<C2>*>(smem));
-        else k3_tile<C3>(R, items[i].tile, s, *reinterpret_cast<K3Smem<C3>*>(smem));
-    }
+    const int i = xcd_item(nitems);
+    const SwRep& R = reps[items[i].rep];
+    uint32_t s;
+    if (!rep_runs(R, it, n_sweeps, s)) return;
+    if (R.dim == 2) k3_tile<C2>(R, items[i].tile, s, *reinterpret_cast<K3Smem<C2>*>(smem));
+    else k3_tile<C3>(R, items[i].tile, s, *reinterpret_cast<K3Smem<C3>*>(smem));
 }
 
 // PCC coverage test: tile t of a replica checks its share of the candidate slots
@@ -495,20 +466,10 @@ int launch_k2(const SwRep& h, SwRep* d, hipStream_t stream)
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-int launch_k3a(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream)
-{
-    const int grid = (int)(((int64_t)h.ntiles * h.fbw + kBlock - 1) / kBlock);
-    switch (h.dim * 16 + h.shape) {
-#define L3A(id, D, X, Y, Z) SW_LAUNCH_CASE(id, D, X, Y, Z, k3a_kernel, d, s)
-        SW_SHAPES(L3A)
-        default: return -1;
-    }
-    return hipGetLastError() == hipSuccess ? 0 : -3;
-}
-
 int launch_k3(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream, int per_cu)
 {
-    const int grid = grid_for(h.ntiles, per_cu);
+    (void)per_cu;
+    const int grid = h.ntiles;
     switch (h.dim * 16 + h.shape) {
 #define L3(id, D, X, Y, Z) SW_LAUNCH_CASE(id, D, X, Y, Z, k3_kernel, d, s)
         SW_SHAPES(L3)
@@ -573,10 +534,9 @@ int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, i
         for (int it = 0; it < n_sweeps; ++it) {                                                                      \
             hipLaunchKernelGGL((kb1_kernel<C2, C3>), dim3(nitems), dim3(max(K1Cfg<C2>::NT, K1Cfg<C3>::NT)), 0, stream, reps, items, nitems, it, n_sweeps); \
             hipLaunchKernelGGL((kb2_kernel<C2, C3>), dim3(nitems), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
-            hipLaunchKernelGGL((kb3a_kernel<C2, C3>), dim3(nitems), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
             if (any_pcc)                                                                                             \
                 hipLaunchKernelGGL((kbc_kernel<C2, C3>), dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
-            hipLaunchKernelGGL((kb3_kernel<C2, C3>), dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
+            hipLaunchKernelGGL((kb3_kernel<C2, C3>), dim3(nitems), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
             if (any_pcc) {                                                                                           \
                 hipLaunchKernelGGL(kbp_kernel, dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
                 hipLaunchKernelGGL(kbu_kernel, dim3(rgrid), dim3(kBlock), 0, stream, reps, nreps, it, n_sweeps);     \
