@@ -16,6 +16,11 @@ Extra objects on the JSON line:
   cpu_baseline  the CPU oracle (single thread) on a bounded sample
   batched       (--batched) 512 uneven replicas: batched phase launches replayed from a hipGraph
                 vs plain per-lattice launches, site-updates/s each
+  pcc           (--pcc) 64 replicas of 2D L=2048 with probability-changing cluster
+                feedback, batched: site-updates/s and the replicas' mean p
+  serving       (--serving) the first N jobs of the Poisson job stream (rate 50/s)
+                through the continuous-batching server: p50 / p99 latency and
+                aggregate site-updates/s
 
 Usage: python bench.py [--gpus 1] [--steps 200] [--warmup 20] [--no-cpu-baseline]
        [--batched] [--copy-probe]
@@ -57,8 +62,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(workload):
-    """The oracle, untuned, on one sweep of each lattice from its start."""
+def cpu_baseline(workload, sweeps: int = 3):
+    """The oracle, untuned, on the first sweeps of each lattice from its start."""
     import oracle
 
     oracle.build(force=not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")))
@@ -67,17 +72,18 @@ def cpu_baseline(workload):
     for rep in workload.replicas:
         spins = oracle.init_spins(rep.dim, rep.L, rep.seed)
         thr = oracle.threshold(rep.J, rep.T)
-        oracle.sweep(rep.dim, rep.L, rep.seed, 0, thr, spins)
-        sites += rep.nsites
+        for s in range(sweeps):
+            spins, _ = oracle.sweep(rep.dim, rep.L, rep.seed, s, thr, spins)
+            sites += rep.nsites
     dt = time.perf_counter() - t0
     return {"value": sites / dt, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "sweep 0 of each lattice of the workload (8192^2 at T_c and 256^3 at T=4.5115) "
-                      f"from the seed-1 start, {sites} site-updates in {dt:.1f} s, single thread"}
+            "sample": f"sweeps 0-{sweeps - 1} of each lattice of the workload (8192^2 at T_c and 256^3 at "
+                      f"T=4.5115) from the seed-1 start, {sites} site-updates in {dt:.1f} s, single thread"}
 
 
 def traffic_from_profile(kernel_key: str, launch_sites: int):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if current."""
-    path = os.path.join(ROOT, "profiles", "traffic_pmc.json")
+    path = os.path.join(ROOT, "profiles", PROFILE_PREFIX + "_traffic_pmc.json")
     try:
         with open(path) as f:
             prof = json.load(f)
@@ -92,6 +98,7 @@ def traffic_from_profile(kernel_key: str, launch_sites: int):
 
 
 PROFILE_LATTICES = {2: ("2d_L8192", 8192 * 8192), 3: ("3d_L256", 256 ** 3)}
+PROFILE_PREFIX = "plain_2d8192_3d256"   # the plain sweep workload: 8192^2 at T_c + 256^3 at T=4.5115
 
 
 def _kernel_of(name: str):
@@ -149,7 +156,7 @@ def summarize_profiles(prof_dir: str, out_dir: str, trace_cmd: str, pmc_cmd: str
         k = _kernel_of(name)
         if k:
             trace_means[f"{k[0]}:{k[1]}"] = sum(v) / len(v)
-    with open(os.path.join(out_dir, "sweep_kernel_trace.txt"), "w") as f:
+    with open(os.path.join(out_dir, PROFILE_PREFIX + "_kernel_trace.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
 
     # 2) counters: KiB per dispatch summed over the counter's instances
@@ -193,13 +200,13 @@ def summarize_profiles(prof_dir: str, out_dir: str, trace_cmd: str, pmc_cmd: str
                                        "write_bytes": wb, "trace_mean_us": trace_means.get(f"{key}:{tag}")}
         ratio = f"{(fb + wb) / algo:12.2f}" if algo else f"{'-':>12}"
         lines.append(f"  {fb / 1e6:10.2f} {wb / 1e6:10.2f} {(algo or 0) / 1e6:10.2f} {ratio}  {name[:100]}")
-    with open(os.path.join(out_dir, "sweep_hbm_traffic.txt"), "w") as f:
+    with open(os.path.join(out_dir, PROFILE_PREFIX + "_hbm_traffic.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
-    with open(os.path.join(out_dir, "traffic_pmc.json"), "w") as f:
+    with open(os.path.join(out_dir, PROFILE_PREFIX + "_traffic_pmc.json"), "w") as f:
         json.dump({"source_hash": source_hash(), "fetch_scale": fetch_scale, "write_scale": write_scale,
                    "kernels": kernels}, f, indent=1)
-    print(json.dumps({"written": [os.path.join(out_dir, n) for n in
-                                  ("sweep_kernel_trace.txt", "sweep_hbm_traffic.txt", "traffic_pmc.json")]}))
+    print(json.dumps({"written": [os.path.join(out_dir, PROFILE_PREFIX + n) for n in
+                                  ("_kernel_trace.txt", "_hbm_traffic.txt", "_traffic_pmc.json")]}))
 
 
 COPY_PROBE_BYTES = 256 << 20
@@ -249,6 +256,76 @@ def run_batched(swgpu, workloads, sweeps_batched: int, sweeps_plain: int):
     return out
 
 
+def run_pcc(swgpu, workloads, sweeps: int):
+    """Probability-changing cluster feedback: 64 replicas of 2D L=2048, batched."""
+    import torch
+
+    wl = workloads.pcc(sweeps=sweeps)
+    params = [swgpu.params_from_replica(r) for r in wl.replicas]
+    sites = sum(r.nsites for r in wl.replicas)
+    stream = torch.cuda.Stream()
+    with swgpu.Lattice(params, stream=ctypes.c_void_p(stream.cuda_stream)) as lat:
+        lat.set_mode(swgpu.SW_MODE_BATCHED)
+        lat.sweep(10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.sweep(sweeps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ps = [lat.state(r)[1] for r in range(len(params))]
+    n = len(ps)
+    mean = sum(ps) / n
+    return {"workload": wl.name, "replicas": n, "sites": sites, "sweeps": sweeps, "seconds": dt,
+            "site_updates_per_s": sites * sweeps / dt, "p_mean": mean,
+            "p_std": (sum((p - mean) ** 2 for p in ps) / n) ** 0.5,
+            "p_c_fk_2d": 1.0 - 1.0 / (1.0 + 2.0 ** 0.5)}
+
+
+def run_serving(swgpu, workloads, n_jobs: int, budget_gib: float, slots: int, tick: int):
+    """Open-loop Poisson job stream through the continuous-batching server."""
+    import torch
+
+    jobs = workloads.serving(n_jobs=n_jobs)
+    stream = torch.cuda.Stream()
+    srv = swgpu.Server(int(budget_gib * (1 << 30)), max_slots=slots, sweeps_per_tick=tick,
+                       stream=ctypes.c_void_p(stream.cuda_stream))
+    ids = []
+    nxt = 0
+    wall0 = last_log = time.perf_counter()
+    t0 = srv.now()
+    while True:
+        now = srv.now() - t0
+        while nxt < len(jobs) and jobs[nxt].arrival <= now:
+            j = jobs[nxt]
+            ids.append(srv.submit(swgpu.params_from_replica(j.replica), j.sweeps))
+            nxt += 1
+        active = srv.step()
+        if time.perf_counter() - last_log > 10.0:
+            last_log = time.perf_counter()
+            log(f"serving: {nxt} submitted, {srv.stats()['done']} done, {active} queued or running")
+        if active == 0:
+            if nxt == len(jobs):
+                break
+            time.sleep(max(0.0, jobs[nxt].arrival - (srv.now() - t0)))
+    wall = time.perf_counter() - wall0
+    lat = []
+    for jid in ids:
+        if srv.poll(jid) == "done":
+            r = srv.result(jid)
+            lat.append(r["t_done"] - r["t_submit"])
+    st = srv.stats()
+    srv.close()
+    lat.sort()
+
+    def pct(q):
+        return lat[min(len(lat) - 1, int(q * len(lat)))] if lat else None
+
+    return {"jobs": n_jobs, "done": st["done"], "rejected": st["rejected"], "rate_per_s": 50.0,
+            "seconds": wall, "site_updates": st["site_updates"], "site_updates_per_s": st["site_updates"] / wall,
+            "p50_latency_s": pct(0.5), "p99_latency_s": pct(0.99), "hbm_budget_gib": budget_gib,
+            "slots": slots, "sweeps_per_tick": tick}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -259,6 +336,13 @@ def main():
     ap.add_argument("--batched", action="store_true", help="also time the 512-replica batched workload")
     ap.add_argument("--batched-sweeps", type=int, default=500)
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--pcc", action="store_true", help="also time the 64 x 2048^2 PCC feedback workload")
+    ap.add_argument("--pcc-sweeps", type=int, default=200)
+    ap.add_argument("--serving", action="store_true", help="also run a Poisson job stream through the server")
+    ap.add_argument("--serving-jobs", type=int, default=40)
+    ap.add_argument("--serving-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serving-slots", type=int, default=64)
+    ap.add_argument("--serving-tick", type=int, default=25)
     ap.add_argument("--summarize", metavar="PROF_DIR",
                     help="write the profiles/ summaries from rocprofv3 runs under PROF_DIR (no GPU needed)")
     ap.add_argument("--summary-commands", nargs=3, metavar=("TRACE", "PMC", "COPY"), default=("?", "?", "?"))
@@ -360,6 +444,11 @@ def main():
         lat.close()
     if args.batched:
         result["batched"] = run_batched(swgpu, workloads, args.batched_sweeps, max(args.batched_sweeps // 10, 2))
+    if args.pcc:
+        result["pcc"] = run_pcc(swgpu, workloads, args.pcc_sweeps)
+    if args.serving:
+        result["serving"] = run_serving(swgpu, workloads, args.serving_jobs, args.serving_budget_gib,
+                                        args.serving_slots, args.serving_tick)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
         result["cpu_baseline"] = cpu_baseline(wl)
