@@ -805,32 +805,67 @@ struct K3Smem {
     uint32_t FBt[C::FBW];        // the tile's border-root bitmap
     uint16_t list[2 * C::FT];    // the tile's border roots (each has a site on a face)
     int cnt;
+    uint32_t wor[kBlock / 64];   // per-wave word for combining coverage marks
 };
 
+// atomicOr(addr, bits) for every lane with `pending`, combined over the wave:
+// lanes with the same target word OR their bits into the wave's LDS word and
+// one of them makes the global atomic.  All lanes of the wave must call it.
+__device__ __forceinline__ void wave_or(uint32_t* addr, uint32_t bits, bool pending, uint32_t* wscr)
+{
+    const int lane = threadIdx.x & 63;
+    while (true) {
+        const uint64_t bal = __ballot(pending);
+        if (!bal) break;
+        const int first = __builtin_ctzll(bal);
+        const uint64_t lead = __shfl((uint64_t)(uintptr_t)addr, first, 64);
+        bool leader = false;
+        if (pending && (uint64_t)(uintptr_t)addr == lead) {
+            atomicOr(wscr, bits);
+            pending = false;
+            leader = lane == first;
+        }
+        wave_lds_sync();
+        if (leader) {
+            atomicOr(addr, *wscr);
+            *wscr = 0;
+        }
+        wave_lds_sync();
+    }
+}
+
+// PCC coverage: if the cluster `root` is a candidate of axis a in this sweep,
+// the bit of coordinate crd of its axis-a bitmap (all lanes of the wave call it)
 template <class C>
-__device__ __forceinline__ void pcc_mark(const SwRep& R, uint32_t root, const uint32_t crd[3], uint64_t tag,
-                                         uint32_t bw, uint32_t nslots)
+__device__ __forceinline__ void pcc_mark(const SwRep& R, uint32_t root, bool valid, const uint32_t crd[3], uint64_t tag,
+                                         uint32_t bw, uint32_t nslots, uint32_t* wscr)
 {
 #pragma unroll
     for (int a = 0; a < C::D; ++a) {
-        const uint64_t c = R.cand[(size_t)a * R.N + root];
-        if ((c & 0xFFFFFFFF00000000ull) != tag) continue;
-        const uint32_t slot = ~(uint32_t)c;
-        if (slot >= nslots) {
-            flag_error(R, ERR_SLOT);
-            continue;
+        bool pending = false;
+        uint32_t* word = nullptr;
+        if (valid) {
+            const uint64_t c = R.cand[(size_t)a * R.N + root];
+            if ((c & 0xFFFFFFFF00000000ull) == tag) {
+                const uint32_t slot = ~(uint32_t)c;
+                if (slot < nslots) {
+                    word = R.bmp + ((size_t)a * nslots + slot) * bw + (crd[a] >> 5);
+                    pending = true;
+                } else {
+                    flag_error(R, ERR_SLOT);
+                }
+            }
         }
-        uint32_t* bm = R.bmp + ((size_t)a * nslots + slot) * bw;
-        atomicOr(&bm[crd[a] >> 5], 1u << (crd[a] & 31u));
+        wave_or(word, 1u << (crd[a] & 31u), pending, wscr);
     }
 }
 
 // new spin byte of the site with tile-local index k and stored label v;
-// writes the final label / coverage marks when asked for
+// writes the final label when asked for and returns the cluster root (for
+// the coverage marks)
 template <class C>
 __device__ __forceinline__ uint32_t k3_site(const SwRep& R, const K3Smem<C>& sm, const TileGeo& g, uint32_t v, int k,
-                                            uint32_t gi, bool labels, bool pcc, uint64_t tag, uint32_t bw,
-                                            uint32_t nslots)
+                                            uint32_t gi, bool labels, bool pcc, uint32_t& root_out)
 {
     const uint32_t lr = v;
     if (lr > (uint32_t)k) {                 // a tile root precedes its sites
@@ -847,11 +882,7 @@ __device__ __forceinline__ uint32_t k3_site(const SwRep& R, const K3Smem<C>& sm,
             root = 0;
         }
         if (labels) R.lab32[gi] = (int32_t)root;
-        if (pcc) {
-            const uint32_t crd[3] = {(uint32_t)(g.x0 + k % C::TX), (uint32_t)(g.y0 + (k / C::TX) % C::TY),
-                                     (uint32_t)(g.z0 + k / (C::TX * C::TY))};
-            pcc_mark<C>(R, root, crd, tag, bw, nslots);
-        }
+        root_out = root;
     }
     return bit ? 0x01u : 0xFFu;
 }
@@ -886,6 +917,7 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
 
     // 1) the tile's border roots into a list; the flip bits of its own rows
     if (tid == 0) sm.cnt = 0;
+    if (tid < kBlock / 64) sm.wor[tid] = 0;
     for (int w = tid; w < C::FBW; w += blockDim.x) sm.BF[w] = 0;
     __syncthreads();
     for (int w = tid; w < C::FBW; w += blockDim.x) {
@@ -926,33 +958,49 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
     }
     __syncthreads();
 
-    // 3) new spins
+    // 3) new spins; coverage marks of the PCC candidates (every lane of a
+    //    wave runs the same iterations, for the combined atomics)
     const uint64_t tag = (uint64_t)(s + 1u) << 32;
     const uint32_t bw = (L + 31u) / 32u;               // bitmap words per candidate
     const uint32_t nslots = (C::D == 3) ? L * L : L;   // candidates per axis
+    uint32_t* wscr = &sm.wor[tid >> 6];
     if (quads) {
 #pragma unroll
         for (int j = 0; j < QPT; ++j) {
             const int qd = tid + kBlock * j;
             const int r = qd / QR, xq = (qd % QR) * 4;
             const int ly = r % C::TY, lz = r / C::TY;
-            if (ly >= g.wy || lz >= g.wz || xq >= g.wx) continue;
+            const bool valid = ly < g.wy && lz < g.wz && xq < g.wx;
             const uint32_t gi = (uint32_t)(g.x0 + xq) + L * ((uint32_t)(g.y0 + ly) + L * (uint32_t)(g.z0 + lz));
             const uint2 v = lv[j];
             const int k = r * C::TX + xq;
-            uint32_t out = k3_site<C>(R, sm, g, v.x & 0xFFFFu, k, gi, labels, pcc, tag, bw, nslots);
-            out |= k3_site<C>(R, sm, g, v.x >> 16, k + 1, gi + 1, labels, pcc, tag, bw, nslots) << 8;
-            out |= k3_site<C>(R, sm, g, v.y & 0xFFFFu, k + 2, gi + 2, labels, pcc, tag, bw, nslots) << 16;
-            out |= k3_site<C>(R, sm, g, v.y >> 16, k + 3, gi + 3, labels, pcc, tag, bw, nslots) << 24;
-            *reinterpret_cast<uint32_t*>(R.spins + gi) = out;
+            uint32_t out = 0;
+            for (int i = 0; i < 4; ++i) {
+                uint32_t root = 0;
+                if (valid) {
+                    const uint32_t vi = (i == 0) ? (v.x & 0xFFFFu) : (i == 1) ? (v.x >> 16) : (i == 2) ? (v.y & 0xFFFFu) : (v.y >> 16);
+                    out |= k3_site<C>(R, sm, g, vi, k + i, gi + (uint32_t)i, labels, pcc, root) << (8 * i);
+                }
+                if (pcc) {
+                    const uint32_t crd[3] = {(uint32_t)(g.x0 + xq + i), (uint32_t)(g.y0 + ly), (uint32_t)(g.z0 + lz)};
+                    pcc_mark<C>(R, root, valid, crd, tag, bw, nslots, wscr);
+                }
+            }
+            if (valid) *reinterpret_cast<uint32_t*>(R.spins + gi) = out;
         }
     } else {
-        for (int k = tid; k < C::TS; k += blockDim.x) {
+        for (int k0 = 0; k0 < C::TS; k0 += kBlock) {
+            const int k = k0 + tid;
             const int xk = k % C::TX, r = k / C::TX;
             const int ly = r % C::TY, lz = r / C::TY;
-            if (ly >= g.wy || lz >= g.wz || xk >= g.wx) continue;
+            const bool valid = ly < g.wy && lz < g.wz && xk < g.wx;
             const uint32_t gi = (uint32_t)(g.x0 + xk) + L * ((uint32_t)(g.y0 + ly) + L * (uint32_t)(g.z0 + lz));
-            R.spins[gi] = (int8_t)k3_site<C>(R, sm, g, R.lab16[gi], k, gi, labels, pcc, tag, bw, nslots);
+            uint32_t root = 0;
+            if (valid) R.spins[gi] = (int8_t)k3_site<C>(R, sm, g, R.lab16[gi], k, gi, labels, pcc, root);
+            if (pcc) {
+                const uint32_t crd[3] = {(uint32_t)(g.x0 + xk), (uint32_t)(g.y0 + ly), (uint32_t)(g.z0 + lz)};
+                pcc_mark<C>(R, root, valid, crd, tag, bw, nslots, wscr);
+            }
         }
     }
     __syncthreads();
