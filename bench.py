@@ -76,7 +76,14 @@ def cpu_baseline(workload, sweeps: int = 3):
             spins, _ = oracle.sweep(rep.dim, rep.L, rep.seed, s, thr, spins)
             sites += rep.nsites
     dt = time.perf_counter() - t0
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": sites / dt, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
+            "host_cpu": model, "host_threads": os.cpu_count(),
             "sample": f"sweeps 0-{sweeps - 1} of each lattice of the workload (8192^2 at T_c and 256^3 at "
                       f"T=4.5115) from the seed-1 start, {sites} site-updates in {dt:.1f} s, single thread"}
 
