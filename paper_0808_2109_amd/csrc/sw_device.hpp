@@ -31,6 +31,10 @@
 namespace sw {
 
 constexpr int kBlock = 256;            // threads per workgroup (4 wave64)
+#ifndef SW_K3_THREADS
+#define SW_K3_THREADS 256
+#endif
+constexpr int kK3Block = SW_K3_THREADS;  // threads per K3 workgroup
 constexpr uint32_t kTagInit = 0, kTagBond = 1, kTagRefine = 2, kTagFlip = 3;
 
 enum : uint32_t { FLAG_SERIES = 1u, FLAG_KEEP = 2u, FLAG_PCC = 4u };
@@ -141,8 +145,9 @@ struct TileCfg {
     static constexpr int NB = TX / 16;        // Philox bond blocks per aligned row
     static_assert(TX == 32 || TX == 64, "a wave64 covers whole tile rows");
     static_assert(TS % kBlock == 0, "whole sites per thread");
+    static_assert(TS % (4 * kK3Block) == 0, "whole quads of sites per K3 thread");
     static_assert(NR <= kBlock, "one thread per row for the halo column");
-    static_assert(TS <= 65536, "tile-local labels are 16-bit");
+    static_assert(TS <= 8192, "tile-local labels fit 13 bits of the merge keys");
 };
 
 struct TileGeo {
@@ -339,6 +344,9 @@ __device__ __forceinline__ uint32_t bytes_eq(uint32_t x, uint32_t y4)
     return ~(((z & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | z) & 0x80808080u;
 }
 
+// nonzero when some byte of v is zero (exact as a whole-word test)
+__device__ __forceinline__ uint32_t has_zero_byte(uint32_t v) { return (v - 0x01010101u) & ~v & 0x80808080u; }
+
 // top bits of the four bytes (bits 7, 15, 23, 31) -> bits 0..3
 __device__ __forceinline__ uint32_t byte_msbs(uint32_t m) { return (((m >> 7) * 0x00204081u) >> 21) & 0xFu; }
 
@@ -473,6 +481,9 @@ __device__ inline uint32_t part_bonds(uint32_t eq, uint32_t lbase, int n, bool a
         const uint32_t blk = lbase >> 4;
         const U4 q = philox10(blk, 0u, s, kTagBond, k0, k1);
         uint32_t bits = nibbles4(bytes_lt(q.x, y4), bytes_lt(q.y, y4), bytes_lt(q.z, y4), bytes_lt(q.w, y4)) & eq;
+        // a byte equal to thr >> 24 (1 in 256 links) needs the low 24 bits
+        if (!(has_zero_byte(q.x ^ y4) | has_zero_byte(q.y ^ y4) | has_zero_byte(q.z ^ y4) | has_zero_byte(q.w ^ y4)))
+            return bits;
         uint32_t ties = nibbles4(bytes_eq(q.x, y4), bytes_eq(q.y, y4), bytes_eq(q.z, y4), bytes_eq(q.w, y4)) & eq;
         while (ties) {
             const int k = __ffs(ties) - 1;
@@ -611,44 +622,46 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
         const int lane = tid & 63, wave = tid >> 6;
         uint32_t* ring = sm.ring[wave];
         uint32_t tail = 0, head = 0;
+        // a queued union is (x, row, direction); its two run starts are found
+        // when it is joined, where every lane of the wave has one
+        auto join = [&](uint32_t e) {
+            const int x = (int)(e & 63u), rr = (int)((e >> 6) & 63u);
+            const int st = (e >> 12) ? C::TY : 1;
+            lds_join(sm.par, rr * C::TX + start_at(sm.SS[rr], x), (rr + st) * C::TX + start_at(sm.SS[rr + st], x));
+        };
 #pragma unroll
         for (int dd = 1; dd < C::D; ++dd) {
-            const int step = (dd == 1) ? 1 : C::TY;
             const bool inner = rowok && ((dd == 1) ? (ly < g.wy - 1) : (lz < g.wz - 1));
-            uint64_t U = 0, SSp = 0;
+            uint32_t U16 = 0;                                    // this part's unions, bit j = site xp + j
             if (inner) {
-                SSp = sm.SS[r + step];
+                const uint64_t SSp = sm.SS[r + ((dd == 1) ? 1 : C::TY)];
                 const uint64_t V = opn[dd];
                 const uint64_t Mc = ~(SS | SSp);                 // neither row starts a run here
                 const uint64_t A = V | Mc;
                 const uint64_t carry = (A + V) ^ A ^ V;          // an open bond earlier in the stretch
-                U = V & ~(Mc & carry) & (0xFFFFull << xp);
+                U16 = (uint32_t)((V & ~(Mc & carry)) >> xp) & 0xFFFFu;
             }
-            while (__ballot(U != 0ull)) {
-                const bool want = U != 0ull;
-                uint32_t pr = 0;
+            const uint32_t tagbits = ((uint32_t)r << 6) | ((uint32_t)(dd - 1) << 12) | (uint32_t)xp;
+            while (__ballot(U16 != 0u)) {
+                const bool want = U16 != 0u;
+                uint32_t e = 0;
                 if (want) {
-                    const int x = __builtin_ctzll(U);
-                    U &= U - 1ull;
-                    pr = (uint32_t)(r * C::TX + start_at(SS, x)) | ((uint32_t)((r + step) * C::TX + start_at(SSp, x)) << 16);
+                    e = tagbits + (uint32_t)__builtin_ctz(U16);
+                    U16 &= U16 - 1u;
                 }
                 const uint64_t bal = __ballot(want);
-                if (want) ring[(tail + (uint32_t)lanes_below(bal)) & (kRing - 1)] = pr;
+                if (want) ring[(tail + (uint32_t)lanes_below(bal)) & (kRing - 1)] = e;
                 tail += (uint32_t)__popcll(bal);
                 if (tail - head >= 64u) {
                     wave_lds_sync();
-                    const uint32_t e = ring[(head + (uint32_t)lane) & (kRing - 1)];
-                    lds_join(sm.par, (int)(e & 0xFFFFu), (int)(e >> 16));
+                    join(ring[(head + (uint32_t)lane) & (kRing - 1)]);
                     head += 64u;
                     wave_lds_sync();
                 }
             }
         }
         wave_lds_sync();
-        if ((uint32_t)lane < tail - head) {
-            const uint32_t e = ring[(head + (uint32_t)lane) & (kRing - 1)];
-            lds_join(sm.par, (int)(e & 0xFFFFu), (int)(e >> 16));
-        }
+        if ((uint32_t)lane < tail - head) join(ring[(head + (uint32_t)lane) & (kRing - 1)]);
     }
     __syncthreads();
 
@@ -668,11 +681,12 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
         const int last = 63 - __clzll((long long)SS);
         const bool xout = (opn[0] >> (g.wx - 1)) & 1ull;
         uint32_t cur = (uint32_t)lds_root(sm.par, rowk + start_at(SS, xp));
+        const uint32_t ss16 = (uint32_t)(SS >> xp) & (uint32_t)low_bits(np);   // run starts of the part
         uint32_t pk[8];
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-            const int x = xp + j;
-            if (x < g.wx && ((SS >> x) & 1ull)) {
+            if ((ss16 >> j) & 1u) {
+                const int x = xp + j;
                 if (j > 0) cur = (uint32_t)lds_root(sm.par, rowk + x);
                 bool b = nearrow || x == 0 || (x == last && xout);
                 if (!b && cross) {
@@ -732,9 +746,9 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
 }
 
 // --------------------------------------------------------------------------
-// K2: border merge.  One work item per far-face site f of tile t: when its
-// link across the face is open, the two tile-local roots it joins are united
-// in the global union-find.  Face labels come from the compact face arrays.
+// K2: border merge.  For each far-face site of a tile whose link across the
+// face is open, the two tile-local roots it joins are united in the global
+// union-find.  Face labels come from the compact face arrays.
 // --------------------------------------------------------------------------
 template <class C>
 __device__ __forceinline__ uint32_t tile_site_global(const SwRep& R, int ix, int iy, int iz, uint32_t lr)
@@ -742,51 +756,84 @@ __device__ __forceinline__ uint32_t tile_site_global(const SwRep& R, int ix, int
     return local_to_global<C>(lr, ix * C::TX, iy * C::TY, iz * C::TZ, R.L);
 }
 
+// K2 works one tile per workgroup.  Many open links across a face join the
+// same two tile-local clusters; every distinct (face, near label, far label)
+// triple is entered in an LDS hash set and only its first link makes the
+// global union.
+constexpr uint32_t kK2Empty = 0xFFFFFFFFu;
+
 template <class C>
-__device__ void k2_link(const SwRep& R, int t, int f)
+struct K2Cfg {
+    static constexpr int HBITS = (2 * C::FT <= 256) ? 8 : (2 * C::FT <= 512) ? 9 : (2 * C::FT <= 1024) ? 10
+                               : (2 * C::FT <= 2048) ? 11 : 12;
+    static constexpr int H = 1 << HBITS;   // hash slots: at least twice the face sites
+    static_assert(H >= 2 * C::FT, "hash set too small");
+};
+
+template <class C>
+struct K2Smem {
+    uint32_t keys[K2Cfg<C>::H];
+};
+
+// true for the first caller with this key (keys < 2^28; the set is never full)
+template <class C>
+__device__ __forceinline__ bool k2_first(K2Smem<C>& sm, uint32_t key)
 {
-    int d, fb, wbase;
-    if (f < C::F0) {
-        d = 0;
-        fb = f;
-        wbase = 0;
-    } else if (f < C::F0 + C::F1) {
-        d = 1;
-        fb = f - C::F0;
-        wbase = C::W0;
-    } else {
-        d = 2;
-        fb = f - C::F0 - C::F1;
-        wbase = C::W0 + C::W1;
+    constexpr uint32_t mask = K2Cfg<C>::H - 1;
+    uint32_t h = (key * 0x9E3779B1u) >> (32 - K2Cfg<C>::HBITS);
+    while (true) {
+        const uint32_t old = atomicCAS(&sm.keys[h], kK2Empty, key);
+        if (old == kK2Empty) return true;
+        if (old == key) return false;
+        h = (h + 1u) & mask;
     }
+}
+
+template <class C>
+__device__ void k2_tile(const SwRep& R, int t, K2Smem<C>& sm)
+{
+    const int tid = threadIdx.x;
+    for (int i = tid; i < K2Cfg<C>::H; i += blockDim.x) sm.keys[i] = kK2Empty;
+    __syncthreads();
     const uint32_t* xb = R.xbits + (size_t)t * C::XW;
-    if (!((xb[wbase + (fb >> 5)] >> (fb & 31)) & 1u)) return;
     const int ix = t % R.ntx, iy = (t / R.ntx) % R.nty, iz = t / (R.ntx * R.nty);
-    int jx = ix, jy = iy, jz = iz;
-    if (d == 0) jx = (ix + 1 == R.ntx) ? 0 : ix + 1;
-    else if (d == 1) jy = (iy + 1 == R.nty) ? 0 : iy + 1;
-    else jz = (iz + 1 == R.ntz) ? 0 : iz + 1;
-    const int tn = jx + R.ntx * (jy + R.nty * jz);
     const uint16_t* farf = R.face + (size_t)t * (2 * C::FT) + C::FT;
-    const uint16_t* nearf = R.face + (size_t)tn * (2 * C::FT);
-    const uint32_t la = farf[f], lb = nearf[f];
-    // the previous link along the face (first in-face axis) joining the same
-    // two tile-local clusters makes this union redundant
-    const int first = (d == 0) ? fb % C::TY : fb % C::TX;
-    if (first > 0 && ((xb[wbase + ((fb - 1) >> 5)] >> ((fb - 1) & 31)) & 1u) && farf[f - 1] == la &&
-        nearf[f - 1] == lb)
-        return;
-    if (la >= (uint32_t)C::TS || lb >= (uint32_t)C::TS) {
-        flag_error(R, ERR_TILE_LABEL);
-        return;
+    for (int f = tid; f < C::FT; f += blockDim.x) {
+        int d, fb, wbase;
+        if (f < C::F0) {
+            d = 0;
+            fb = f;
+            wbase = 0;
+        } else if (f < C::F0 + C::F1) {
+            d = 1;
+            fb = f - C::F0;
+            wbase = C::W0;
+        } else {
+            d = 2;
+            fb = f - C::F0 - C::F1;
+            wbase = C::W0 + C::W1;
+        }
+        if (!((xb[wbase + (fb >> 5)] >> (fb & 31)) & 1u)) continue;
+        int jx = ix, jy = iy, jz = iz;
+        if (d == 0) jx = (ix + 1 == R.ntx) ? 0 : ix + 1;
+        else if (d == 1) jy = (iy + 1 == R.nty) ? 0 : iy + 1;
+        else jz = (iz + 1 == R.ntz) ? 0 : iz + 1;
+        const int tn = jx + R.ntx * (jy + R.nty * jz);
+        const uint32_t la = farf[f], lb = R.face[(size_t)tn * (2 * C::FT) + f];
+        if (la >= (uint32_t)C::TS || lb >= (uint32_t)C::TS) {
+            flag_error(R, ERR_TILE_LABEL);
+            continue;
+        }
+        if (!k2_first<C>(sm, la | (lb << 13) | ((uint32_t)d << 26))) continue;
+        const uint32_t ra = tile_site_global<C>(R, ix, iy, iz, la);
+        const uint32_t rb = tile_site_global<C>(R, jx, jy, jz, lb);
+        if (ra >= R.N || rb >= R.N) {
+            flag_error(R, ERR_TILE_LABEL);
+            continue;
+        }
+        g_unite(R, R.par, (int)ra, (int)rb);
     }
-    const uint32_t ra = tile_site_global<C>(R, ix, iy, iz, la);
-    const uint32_t rb = tile_site_global<C>(R, jx, jy, jz, lb);
-    if (ra >= R.N || rb >= R.N) {
-        flag_error(R, ERR_TILE_LABEL);
-        return;
-    }
-    g_unite(R, R.par, (int)ra, (int)rb);
+    __syncthreads();
 }
 
 // --------------------------------------------------------------------------
@@ -805,7 +852,7 @@ struct K3Smem {
     uint32_t FBt[C::FBW];        // the tile's border-root bitmap
     uint16_t list[2 * C::FT];    // the tile's border roots (each has a site on a face)
     int cnt;
-    uint32_t wor[kBlock / 64];   // per-wave word for combining coverage marks
+    uint32_t wor[kK3Block / 64]; // per-wave word for combining coverage marks
 };
 
 // atomicOr(addr, bits) for every lane with `pending`, combined over the wave:
@@ -898,7 +945,7 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
     const bool pcc = (R.flags & FLAG_PCC) != 0;
     constexpr int CAP = 2 * C::FT;
     constexpr int QR = C::TX / 4;                       // quads of sites per row
-    constexpr int QPT = C::TS / 4 / kBlock;             // quads per thread (blockDim = kBlock)
+    constexpr int QPT = C::TS / 4 / kK3Block;           // quads per thread (blockDim = kK3Block)
     const bool quads = (L & 3u) == 0;                   // then every row and the tile width are multiples of 4
 
     // 0) the tile's labels, four sites per thread and load, issued first so
@@ -906,7 +953,7 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
     uint2 lv[QPT];
 #pragma unroll
     for (int j = 0; j < QPT; ++j) {
-        const int qd = tid + kBlock * j;
+        const int qd = tid + kK3Block * j;
         const int r = qd / QR, xq = (qd % QR) * 4;
         const int ly = r % C::TY, lz = r / C::TY;
         lv[j] = make_uint2(0u, 0u);
@@ -917,7 +964,7 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
 
     // 1) the tile's border roots into a list; the flip bits of its own rows
     if (tid == 0) sm.cnt = 0;
-    if (tid < kBlock / 64) sm.wor[tid] = 0;
+    if (tid < kK3Block / 64) sm.wor[tid] = 0;
     for (int w = tid; w < C::FBW; w += blockDim.x) sm.BF[w] = 0;
     __syncthreads();
     for (int w = tid; w < C::FBW; w += blockDim.x) {
@@ -967,7 +1014,7 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
     if (quads) {
 #pragma unroll
         for (int j = 0; j < QPT; ++j) {
-            const int qd = tid + kBlock * j;
+            const int qd = tid + kK3Block * j;
             const int r = qd / QR, xq = (qd % QR) * 4;
             const int ly = r % C::TY, lz = r / C::TY;
             const bool valid = ly < g.wy && lz < g.wz && xq < g.wx;
@@ -989,7 +1036,7 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
             if (valid) *reinterpret_cast<uint32_t*>(R.spins + gi) = out;
         }
     } else {
-        for (int k0 = 0; k0 < C::TS; k0 += kBlock) {
+        for (int k0 = 0; k0 < C::TS; k0 += kK3Block) {
             const int k = k0 + tid;
             const int xk = k % C::TX, r = k / C::TX;
             const int ly = r % C::TY, lz = r / C::TY;

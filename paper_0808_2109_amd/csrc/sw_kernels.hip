@@ -14,12 +14,12 @@ namespace sw {
 // the pairs (2D shape i, 3D shape i).
 // Every shape has 64 rows (TY * TZ), one per lane of the K1 wave.
 #define SW_SHAPES_2D(X) X(0, 2, 64, 64, 1) X(1, 2, 32, 64, 1)
-#define SW_SHAPES_3D(X) X(0, 3, 32, 8, 8) X(1, 3, 32, 16, 4)
+#define SW_SHAPES_3D(X) X(0, 3, 32, 8, 8) X(1, 3, 64, 8, 8)
 #define SW_SHAPES(X) SW_SHAPES_2D(X) SW_SHAPES_3D(X)
 using Eng0_2D = TileCfg<2, 64, 64, 1>;
 using Eng0_3D = TileCfg<3, 32, 8, 8>;
 using Eng1_2D = TileCfg<2, 32, 64, 1>;
-using Eng1_3D = TileCfg<3, 32, 16, 4>;
+using Eng1_3D = TileCfg<3, 64, 8, 8>;
 #define SW_ENGINE_PAIRS(X) X(0, Eng0_2D, Eng0_3D) X(1, Eng1_2D, Eng1_3D)
 
 constexpr int kNumShapes = 2;
@@ -94,18 +94,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) voi
     if (em) wave_flush_em(e, m, em);
 }
 
+// K2: one workgroup per tile, grid = ntiles (XCD-aware order)
 template <class C>
 __global__ __launch_bounds__(kBlock) void k2_kernel(const SwRep* Rd)
 {
+    __shared__ K2Smem<C> sm;
     const SwRep R = *Rd;
-    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (gid >= (int64_t)R.ntiles * C::FT) return;
-    k2_link<C>(R, (int)(gid / C::FT), (int)(gid % C::FT));
+    k2_tile<C>(R, xcd_item(R.ntiles), sm);
 }
-
 // K3: one workgroup per tile, grid = ntiles (XCD-aware order)
 template <class C>
-__global__ __launch_bounds__(kBlock) void k3_kernel(const SwRep* Rd, uint32_t s)
+__global__ __launch_bounds__(kK3Block) void k3_kernel(const SwRep* Rd, uint32_t s)
 {
     __shared__ K3Smem<C> sm;
     const SwRep R = *Rd;
@@ -302,15 +301,13 @@ template <class C2, class C3>
 __global__ __launch_bounds__(kBlock) void kb2_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
                                                      int n_sweeps)
 {
-    const int i = blockIdx.x;
-    if (i >= nitems) return;
+    __shared__ __align__(16) char smem[cmax2(sizeof(K2Smem<C2>), sizeof(K2Smem<C3>))];
+    const int i = xcd_item(nitems);
     const SwRep& R = reps[items[i].rep];
     uint32_t s;
     if (!rep_runs(R, it, n_sweeps, s)) return;
-    if (R.dim == 2)
-        for (int f = threadIdx.x; f < C2::FT; f += kBlock) k2_link<C2>(R, items[i].tile, f);
-    else
-        for (int f = threadIdx.x; f < C3::FT; f += kBlock) k2_link<C3>(R, items[i].tile, f);
+    if (R.dim == 2) k2_tile<C2>(R, items[i].tile, *reinterpret_cast<K2Smem<C2>*>(smem));
+    else k2_tile<C3>(R, items[i].tile, *reinterpret_cast<K2Smem<C3>*>(smem));
 }
 
 template <class C2, class C3>
@@ -329,7 +326,7 @@ __global__ __launch_bounds__(kBlock) void kbc_kernel(SwRep* reps, const EngineIt
 }
 
 template <class C2, class C3>
-__global__ __launch_bounds__(kBlock) void kb3_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
+__global__ __launch_bounds__(kK3Block) void kb3_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
                                                      int n_sweeps)
 {
     __shared__ __align__(16) char smem[cmax2(sizeof(K3Smem<C2>), sizeof(K3Smem<C3>))];
@@ -457,7 +454,7 @@ int launch_k1(const SwRep& h, SwRep* d, uint32_t s, int64_t* em, hipStream_t str
 
 int launch_k2(const SwRep& h, SwRep* d, hipStream_t stream)
 {
-    const int grid = (int)(((int64_t)h.ntiles * h.ft + kBlock - 1) / kBlock);
+    const int grid = h.ntiles;
     switch (h.dim * 16 + h.shape) {
 #define L2(id, D, X, Y, Z) SW_LAUNCH_CASE(id, D, X, Y, Z, k2_kernel, d)
         SW_SHAPES(L2)
@@ -471,7 +468,12 @@ int launch_k3(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream, int per_
     (void)per_cu;
     const int grid = h.ntiles;
     switch (h.dim * 16 + h.shape) {
-#define L3(id, D, X, Y, Z) SW_LAUNCH_CASE(id, D, X, Y, Z, k3_kernel, d, s)
+#define L3(id, D, X, Y, Z)                                                               \
+    case (D * 16 + id): {                                                               \
+        using C = TileCfg<D, X, Y, Z>;                                                  \
+        hipLaunchKernelGGL(k3_kernel<C>, dim3(grid), dim3(kK3Block), 0, stream, d, s);  \
+        break;                                                                          \
+    }
         SW_SHAPES(L3)
         default: return -1;
     }
@@ -536,7 +538,7 @@ int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, i
             hipLaunchKernelGGL((kb2_kernel<C2, C3>), dim3(nitems), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
             if (any_pcc)                                                                                             \
                 hipLaunchKernelGGL((kbc_kernel<C2, C3>), dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
-            hipLaunchKernelGGL((kb3_kernel<C2, C3>), dim3(nitems), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
+            hipLaunchKernelGGL((kb3_kernel<C2, C3>), dim3(nitems), dim3(kK3Block), 0, stream, reps, items, nitems, it, n_sweeps); \
             if (any_pcc) {                                                                                           \
                 hipLaunchKernelGGL(kbp_kernel, dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
                 hipLaunchKernelGGL(kbu_kernel, dim3(rgrid), dim3(kBlock), 0, stream, reps, nreps, it, n_sweeps);     \
