@@ -46,7 +46,8 @@ ALGO_BYTES_PER_SITE = {
     "k1_bond_label": 3.0,     # read the int8 spin, write the 16-bit tile label
     "k3_flip": 3.0,           # read the 16-bit tile label, write the int8 spin
 }
-KERNEL_SYMBOLS = {"k1_bond_label": "k1_kernel", "k2_merge": "k2_kernel", "k3_flip": "k3_kernel"}
+KERNEL_SYMBOLS = {"k1_bond_label": "k1_kernel", "k2_merge": "k2_kernel", "k3_flip": "k3_kernel",
+                  "k3_resolve": "k3a_kernel"}
 SOURCES = ["paper_0808_2109_amd/csrc/sw_device.hpp", "paper_0808_2109_amd/csrc/sw_kernels.hip"]
 
 

@@ -173,7 +173,8 @@ int sw_set_timing(sw_lattice* h, int32_t enable);
  * Accumulated device time per phase since timing was enabled: ms[k] and
  * launches[k] for k < n (k = 0 bond+tile labelling, 1 border merge, 2 cluster
  * flip, 3 percolation + feedback, 4 measurement, 5 batched sweeps: one
- * replayed graph per call, all phases together).  Synchronises.
+ * replayed graph per call, all phases together, 6 border-root resolution).
+ * Synchronises.
  */
 int sw_get_timing(sw_lattice* h, double* ms, int64_t* launches, int32_t n);
 

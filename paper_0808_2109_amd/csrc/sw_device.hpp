@@ -14,10 +14,10 @@
 //       the two ends of every open link that leaves a tile (the border
 //       reconciliation of Sec. II, in one pass instead of the master's second
 //       labelling or the iterated neighbour exchange).
-//   K3  per tile: find the cluster root of each of the tile's border roots
+//   K3a per tile: find the cluster root of each of the tile's border roots
 //       (the smallest site index of the cluster: the label identity that the
-//       min-label rule of Sec. II.B converges to) and give every site its
-//       cluster's new spin (Sec. I step 3).
+//       min-label rule of Sec. II.B converges to) and that cluster's flip bit.
+//   K3b per tile: give every site its cluster's new spin (Sec. I step 3).
 // plus the extension-rule percolation test and p feedback of Sec. III.
 //
 // Every union hooks the larger root under the smaller one, so the final roots
@@ -71,6 +71,7 @@ struct SwRep {
     uint32_t* xbits;            // ntiles * xwords crossing-link bits
     uint32_t* fbits;            // ntiles * fbw: border roots of each tile (bit per tile-local site)
     uint16_t* face;             // ntiles * 2 * ft: labels of the near, then the far face sites
+    uint32_t* bflip;            // ntiles * fbw: flip bits of each tile's border roots (K3a -> K3b)
     int64_t* series;            // 2 * series_cap
     int64_t* acc;               // 2 scratch accumulators (measure)
     uint64_t* cand;             // PCC: dim * N candidate marks (tag << 32 | ~slot)
@@ -837,21 +838,70 @@ __device__ void k2_tile(const SwRep& R, int t, K2Smem<C>& sm)
 }
 
 // --------------------------------------------------------------------------
-// K3: cluster flip.  The tile's border roots (its border bitmap) find their
-// cluster roots, the smallest site index of the cluster (the label identity
-// that the min-label rule of Sec. II.B converges to), and that cluster's flip
-// bit; an interior root is its own cluster label and takes its flip bit from
-// the tile's own rows of flip bits.  Every site then gets its cluster's new
-// spin.  Optionally writes the final labels and marks percolation coverage
-// (PCC).
+// K3a: border roots, one wave per tile.  The roots in the tile's border
+// bitmap are compacted into a list; each lane takes one at a time, finds its
+// cluster root (the smallest site index of the cluster: the label identity
+// that the min-label rule of Sec. II.B converges to), keeps it as parent when
+// labels are written, and records the cluster's flip bit.
+// --------------------------------------------------------------------------
+template <class C>
+struct K3aSmem {
+    uint16_t list[2 * C::FT];    // the tile's border roots (each has a site on a face)
+    uint32_t BF[C::FBW];
+    int cnt;
+};
+
+template <class C>
+__device__ void k3a_tile(const SwRep& R, int t, uint32_t s, K3aSmem<C>& sm)
+{
+    constexpr int CAP = 2 * C::FT;
+    const int lane = threadIdx.x & 63;
+    const TileGeo g = tile_geo<C>(R, t);
+    const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
+    const bool keep = R.lab32 != nullptr || (R.flags & FLAG_PCC) != 0;
+    if (lane == 0) sm.cnt = 0;
+    for (int w = lane; w < C::FBW; w += 64) sm.BF[w] = 0;
+    wave_lds_sync();
+    for (int w = lane; w < C::FBW; w += 64) {
+        uint32_t m = R.fbits[(size_t)t * C::FBW + w];
+        if (!m) continue;
+        int pos = atomicAdd(&sm.cnt, __popc(m));
+        while (m) {
+            const int b = __ffs(m) - 1;
+            m &= m - 1u;
+            if (pos < CAP) sm.list[pos] = (uint16_t)(w * 32 + b);
+            ++pos;
+        }
+    }
+    wave_lds_sync();
+    const int nb = sm.cnt;
+    if (nb > CAP && lane == 0) flag_error(R, ERR_TILE_LABEL);   // more border roots than face sites
+    for (int i = lane; i < min(nb, CAP); i += 64) {
+        const uint32_t lr = sm.list[i];
+        const uint32_t gi = local_to_global<C>(lr, g.x0, g.y0, g.z0, R.L);
+        if (gi >= R.N) {
+            flag_error(R, ERR_TILE_LABEL);
+            continue;
+        }
+        const uint32_t root = ro_find(R, gi);
+        if (keep && root != gi) R.par[gi] = (int32_t)root;
+        if (flip_bit(root, s, k0, k1)) atomicOr(&sm.BF[lr >> 5], 1u << (lr & 31u));
+    }
+    wave_lds_sync();
+    for (int w = lane; w < C::FBW; w += 64) R.bflip[(size_t)t * C::FBW + w] = sm.BF[w];
+}
+
+// --------------------------------------------------------------------------
+// K3b: cluster flip.  A border root's flip bit comes from K3a; an interior
+// root is its own cluster label and takes its flip bit from the tile's own
+// rows of flip bits.  Every site gets its cluster's new spin.  Optionally
+// writes the final labels and marks percolation coverage (PCC).
 // --------------------------------------------------------------------------
 template <class C>
 struct K3Smem {
     uint64_t RF[C::NR];          // flip bits of the tile's own sites, one mask per row
     uint32_t BF[C::FBW];         // flip bits of the tile's border roots
     uint32_t FBt[C::FBW];        // the tile's border-root bitmap
-    uint16_t list[2 * C::FT];    // the tile's border roots (each has a site on a face)
-    int cnt;
     uint32_t wor[kK3Block / 64]; // per-wave word for combining coverage marks
 };
 
@@ -923,7 +973,7 @@ __device__ __forceinline__ uint32_t k3_site(const SwRep& R, const K3Smem<C>& sm,
     const uint32_t bit = border ? (sm.BF[lr >> 5] >> (lr & 31u)) & 1u : (uint32_t)(sm.RF[lr / C::TX] >> (lr % C::TX)) & 1u;
     if (labels || pcc) {
         uint32_t root = local_to_global<C>(lr, g.x0, g.y0, g.z0, R.L);
-        if (border) root = (uint32_t)R.par[root];   // set to the cluster root above
+        if (border) root = (uint32_t)R.par[root];   // set to the cluster root by K3a
         if (root >= R.N) {
             flag_error(R, ERR_PARENT);
             root = 0;
@@ -943,13 +993,12 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
     const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
     const bool labels = R.lab32 != nullptr;
     const bool pcc = (R.flags & FLAG_PCC) != 0;
-    constexpr int CAP = 2 * C::FT;
     constexpr int QR = C::TX / 4;                       // quads of sites per row
     constexpr int QPT = C::TS / 4 / kK3Block;           // quads per thread (blockDim = kK3Block)
     const bool quads = (L & 3u) == 0;                   // then every row and the tile width are multiples of 4
 
     // 0) the tile's labels, four sites per thread and load, issued first so
-    //    that they arrive while the border roots are resolved
+    //    that they arrive while the row flip bits are drawn
     uint2 lv[QPT];
 #pragma unroll
     for (int j = 0; j < QPT; ++j) {
@@ -962,22 +1011,12 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
                                                     L * ((uint32_t)(g.y0 + ly) + L * (uint32_t)(g.z0 + lz)));
     }
 
-    // 1) the tile's border roots into a list; the flip bits of its own rows
-    if (tid == 0) sm.cnt = 0;
+    // 1) the tile's border bitmap and their flip bits (from K3a); the flip
+    //    bits of its own rows
     if (tid < kK3Block / 64) sm.wor[tid] = 0;
-    for (int w = tid; w < C::FBW; w += blockDim.x) sm.BF[w] = 0;
-    __syncthreads();
     for (int w = tid; w < C::FBW; w += blockDim.x) {
-        uint32_t m = R.fbits[(size_t)t * C::FBW + w];
-        sm.FBt[w] = m;
-        if (!m) continue;
-        int pos = atomicAdd(&sm.cnt, __popc(m));
-        while (m) {
-            const int b = __ffs(m) - 1;
-            m &= m - 1u;
-            if (pos < CAP) sm.list[pos] = (uint16_t)(w * 32 + b);
-            ++pos;
-        }
+        sm.FBt[w] = R.fbits[(size_t)t * C::FBW + w];
+        sm.BF[w] = R.bflip[(size_t)t * C::FBW + w];
     }
     if (tid < C::NR) {
         const int ly = tid % C::TY, lz = tid / C::TY;
@@ -985,23 +1024,6 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
         if (ly < g.wy && lz < g.wz)
             rf = row_flips((uint32_t)g.x0 + L * ((uint32_t)(g.y0 + ly) + L * (uint32_t)(g.z0 + lz)), g.wx, s, k0, k1);
         sm.RF[tid] = rf;
-    }
-    __syncthreads();
-
-    // 2) border roots: cluster root (kept as parent when labels are written)
-    //    and the cluster's flip bit
-    const int nb = sm.cnt;
-    if (nb > CAP && tid == 0) flag_error(R, ERR_TILE_LABEL);   // more border roots than face sites
-    for (int i = tid; i < min(nb, CAP); i += blockDim.x) {
-        const uint32_t lr = sm.list[i];
-        const uint32_t gi = local_to_global<C>(lr, g.x0, g.y0, g.z0, (int)L);
-        if (gi >= R.N) {
-            flag_error(R, ERR_TILE_LABEL);
-            continue;
-        }
-        const uint32_t root = ro_find(R, gi);
-        if ((labels || pcc) && root != gi) R.par[gi] = (int32_t)root;
-        if (flip_bit(root, s, k0, k1)) atomicOr(&sm.BF[lr >> 5], 1u << (lr & 31u));
     }
     __syncthreads();
 

@@ -19,6 +19,7 @@ uint64_t device_wallclock_hz();
 
 int launch_k1(const SwRep& h, SwRep* d, uint32_t s, int64_t* em, hipStream_t stream, int per_cu);
 int launch_k2(const SwRep& h, SwRep* d, hipStream_t stream);
+int launch_k3a(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream);
 int launch_k3(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream, int per_cu);
 int launch_cand(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream);
 int launch_perc(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream);

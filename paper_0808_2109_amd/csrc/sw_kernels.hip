@@ -1,8 +1,7 @@
 // sw_kernels.hip -- the HIP kernels of the sweep and their host launchers.
 //
-// Plain path: one launch per phase and replica (K1, K2, K3, and for PCC the
-// candidate, coverage and feedback kernels).  K1 and K3 run one workgroup per
-// tile, K2 one thread per far-face site of every tile.  Batched path: each
+// Plain path: one launch per phase and replica (K1, K2, K3a, K3b, and for PCC
+// the candidate, coverage and feedback kernels), each one workgroup per tile.  Batched path: each
 // phase is one launch over the tiles of all replicas, and the launches of
 // many sweeps are replayed from one hipGraph.
 #include "sw_device.hpp"
@@ -102,7 +101,16 @@ __global__ __launch_bounds__(kBlock) void k2_kernel(const SwRep* Rd)
     const SwRep R = *Rd;
     k2_tile<C>(R, xcd_item(R.ntiles), sm);
 }
-// K3: one workgroup per tile, grid = ntiles (XCD-aware order)
+// K3a: one wave per tile, grid = ntiles
+template <class C>
+__global__ __launch_bounds__(64) void k3a_kernel(const SwRep* Rd, uint32_t s)
+{
+    __shared__ K3aSmem<C> sm;
+    const SwRep R = *Rd;
+    k3a_tile<C>(R, xcd_item(R.ntiles), s, sm);
+}
+
+// K3b: one workgroup per tile, grid = ntiles (XCD-aware order)
 template <class C>
 __global__ __launch_bounds__(kK3Block) void k3_kernel(const SwRep* Rd, uint32_t s)
 {
@@ -326,6 +334,19 @@ __global__ __launch_bounds__(kBlock) void kbc_kernel(SwRep* reps, const EngineIt
 }
 
 template <class C2, class C3>
+__global__ __launch_bounds__(64) void kb3a_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
+                                                  int n_sweeps)
+{
+    __shared__ __align__(16) char smem[cmax2(sizeof(K3aSmem<C2>), sizeof(K3aSmem<C3>))];
+    const int i = xcd_item(nitems);
+    const SwRep& R = reps[items[i].rep];
+    uint32_t s;
+    if (!rep_runs(R, it, n_sweeps, s)) return;
+    if (R.dim == 2) k3a_tile<C2>(R, items[i].tile, s, *reinterpret_cast<K3aSmem<C2>*>(smem));
+    else k3a_tile<C3>(R, items[i].tile, s, *reinterpret_cast<K3aSmem<C3>*>(smem));
+}
+
+template <class C2, class C3>
 __global__ __launch_bounds__(kK3Block) void kb3_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
                                                      int n_sweeps)
 {
@@ -463,6 +484,22 @@ int launch_k2(const SwRep& h, SwRep* d, hipStream_t stream)
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
+int launch_k3a(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream)
+{
+    const int grid = h.ntiles;
+    switch (h.dim * 16 + h.shape) {
+#define L3A(id, D, X, Y, Z)                                                       \
+    case (D * 16 + id): {                                                        \
+        using C = TileCfg<D, X, Y, Z>;                                           \
+        hipLaunchKernelGGL(k3a_kernel<C>, dim3(grid), dim3(64), 0, stream, d, s); \
+        break;                                                                   \
+    }
+        SW_SHAPES(L3A)
+        default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
 int launch_k3(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream, int per_cu)
 {
     (void)per_cu;
@@ -536,6 +573,7 @@ int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, i
         for (int it = 0; it < n_sweeps; ++it) {                                                                      \
             hipLaunchKernelGGL((kb1_kernel<C2, C3>), dim3(nitems), dim3(max(K1Cfg<C2>::NT, K1Cfg<C3>::NT)), 0, stream, reps, items, nitems, it, n_sweeps); \
             hipLaunchKernelGGL((kb2_kernel<C2, C3>), dim3(nitems), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
+            hipLaunchKernelGGL((kb3a_kernel<C2, C3>), dim3(nitems), dim3(64), 0, stream, reps, items, nitems, it, n_sweeps); \
             if (any_pcc)                                                                                             \
                 hipLaunchKernelGGL((kbc_kernel<C2, C3>), dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
             hipLaunchKernelGGL((kb3_kernel<C2, C3>), dim3(nitems), dim3(kK3Block), 0, stream, reps, items, nitems, it, n_sweeps); \

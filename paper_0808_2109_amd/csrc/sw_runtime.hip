@@ -128,11 +128,11 @@ void fill_geometry(SwRep& h, int shape)
     h.ft = shape_ft(h.dim, shape);
 }
 
-// per-tile buffers: crossing bits, border-root bitmaps, face labels
+// per-tile buffers: crossing bits, border-root bitmaps and their flip bits, face labels
 static uint64_t tile_bytes(const SwRep& h)
 {
     const uint64_t nt = (uint64_t)h.ntiles;
-    return nt * (uint64_t)h.xwords * 4 + nt * (uint64_t)h.fbw * 4 + nt * 2 * (uint64_t)h.ft * 2;
+    return nt * (uint64_t)h.xwords * 4 + 2 * nt * (uint64_t)h.fbw * 4 + nt * 2 * (uint64_t)h.ft * 2;
 }
 
 uint64_t footprint_bytes(const sw_params* p, int shape)
@@ -184,16 +184,18 @@ static void dfree(void* p)
 static int alloc_tile_buffers(SwRep& h)
 {
     const size_t nt = (size_t)h.ntiles;
-    h.xbits = h.fbits = nullptr;
+    h.xbits = h.fbits = h.bflip = nullptr;
     h.face = nullptr;
     int rc = dmalloc((void**)&h.xbits, nt * h.xwords * 4, "crossing bits");
     if (!rc) rc = dmalloc((void**)&h.fbits, nt * h.fbw * 4, "border bitmaps");
+    if (!rc) rc = dmalloc((void**)&h.bflip, nt * h.fbw * 4, "border flip bits");
     if (!rc) rc = dmalloc((void**)&h.face, nt * 2 * h.ft * 2, "face labels");
     if (rc) {
         dfree(h.xbits);
         dfree(h.fbits);
+        dfree(h.bflip);
         dfree(h.face);
-        h.xbits = h.fbits = nullptr;
+        h.xbits = h.fbits = h.bflip = nullptr;
         h.face = nullptr;
     }
     return rc;
@@ -207,6 +209,7 @@ void replica_free(ReplicaH& r)
     dfree(r.h.lab32);
     dfree(r.h.xbits);
     dfree(r.h.fbits);
+    dfree(r.h.bflip);
     dfree(r.h.face);
     dfree(r.h.series);
     dfree(r.h.acc);
@@ -218,7 +221,7 @@ void replica_free(ReplicaH& r)
     r.h.spins = nullptr;
     r.h.lab16 = nullptr;
     r.h.par = r.h.lab32 = r.h.pflag = r.h.perc_trace = nullptr;
-    r.h.xbits = r.h.fbits = r.h.bmp = nullptr;
+    r.h.xbits = r.h.fbits = r.h.bflip = r.h.bmp = nullptr;
     r.h.face = nullptr;
     r.h.series = r.h.acc = nullptr;
     r.h.cand = nullptr;
@@ -478,6 +481,7 @@ int plain_sweep(sw_lattice* h, int r, int32_t n)
         }
         TIMED(h, 0, launch_k1(m, d, s, em, h->stream, h->per_cu[0]));
         TIMED(h, 1, launch_k2(m, d, h->stream));
+        TIMED(h, 6, launch_k3a(m, d, s, h->stream));
         if (pcc) TIMED(h, 3, launch_cand(m, d, s, h->stream));
         TIMED(h, 2, launch_k3(m, d, s, h->stream, h->per_cu[2]));
         if (pcc) TIMED(h, 3, launch_perc(m, d, s, h->stream));
@@ -912,6 +916,7 @@ int sw_set_tile_shape(sw_lattice* h, int32_t replica, int32_t shape)
     if (rc) return rc;
     dfree(r.h.xbits);
     dfree(r.h.fbits);
+    dfree(r.h.bflip);
     dfree(r.h.face);
     r.h = probe;
     h->items_dirty = true;

@@ -24,8 +24,8 @@ struct TimedLaunch {
     hipEvent_t a, b;
 };
 
-// timed phases: 0 K1, 1 K2, 2 K3, 3 PCC, 4 measurement, 5 batched sweeps
-constexpr int kPhases = 6;
+// timed phases: 0 K1, 1 K2, 2 K3b, 3 PCC, 4 measurement, 5 batched sweeps, 6 K3a
+constexpr int kPhases = 7;
 
 int fail(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);

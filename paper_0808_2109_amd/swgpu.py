@@ -21,7 +21,7 @@ SW_OK, SW_EINVAL, SW_ENOMEM, SW_EHIP, SW_EBUSY, SW_ENOTFOUND, SW_ECANCELLED, SW_
 SW_RECORD_SERIES, SW_KEEP_LABELS, SW_PCC = 1, 2, 4
 SW_MODE_PLAIN, SW_MODE_BATCHED = 0, 1
 JOB_STATES = {0: "queued", 1: "running", 2: "done", 3: "rejected", 4: "cancelled"}
-PHASES = ("k1_bond_label", "k2_merge", "k3_flip", "pcc", "measure", "batched")
+PHASES = ("k1_bond_label", "k2_merge", "k3_flip", "pcc", "measure", "batched", "k3_resolve")
 
 
 class SwError(RuntimeError):
