@@ -322,7 +322,8 @@ int handle_sync(sw_lattice* h)
     return SW_OK;
 }
 
-// bring the host mirrors up to date after device-side updates
+// bring the host mirrors up to date after device-side updates (batched
+// sweeps, PCC feedback); waits for the stream and checks the error word
 int sync_mirror(sw_lattice* h)
 {
     int rc = handle_sync(h);
@@ -340,6 +341,14 @@ int sync_mirror(sw_lattice* h)
     }
     h->mirror_stale = false;
     return SW_OK;
+}
+
+// as sync_mirror, but a no-op (no wait) while the mirrors are current, so
+// that back-to-back sweep calls keep the stream busy; a device error then
+// surfaces at the next call that reads results
+int refresh_mirror(sw_lattice* h)
+{
+    return h->mirror_stale ? sync_mirror(h) : SW_OK;
 }
 
 // write the full host mirror of replica r to its device descriptor (synchronous)
@@ -376,7 +385,7 @@ int ensure_capacity(sw_lattice* h, int r, uint64_t need)
     if (need > 0xFFFFFFF0ull) return fail(SW_EINVAL, "sweep index overflow");
     bool changed = false;
     if ((m.flags & FLAG_SERIES) && need > m.series_cap) {
-        int rc = sync_mirror(h);
+        int rc = refresh_mirror(h);
         if (rc) return rc;
         const uint32_t nc = (uint32_t)std::max<uint64_t>(need, 2ull * m.series_cap);
         rc = grow((void**)&m.series, m.series_cap, nc, 16, h->stream, "series");
@@ -385,7 +394,7 @@ int ensure_capacity(sw_lattice* h, int r, uint64_t need)
         changed = true;
     }
     if ((m.flags & FLAG_PCC) && need > m.trace_cap) {
-        int rc = sync_mirror(h);
+        int rc = refresh_mirror(h);
         if (rc) return rc;
         const uint32_t nc = (uint32_t)std::max<uint64_t>(need, 2ull * m.trace_cap);
         rc = grow((void**)&m.perc_trace, m.trace_cap, nc, 4, h->stream, "percolation trace");
@@ -463,7 +472,7 @@ int timing_collect(sw_lattice* h)
 // ---------------------------------------------------------------------------
 int plain_sweep(sw_lattice* h, int r, int32_t n)
 {
-    int rc = sync_mirror(h);
+    int rc = refresh_mirror(h);
     if (rc) return rc;
     ReplicaH& rep = h->reps[r];
     SwRep& m = rep.h;
@@ -486,6 +495,7 @@ int plain_sweep(sw_lattice* h, int r, int32_t n)
         TIMED(h, 2, launch_k3(m, d, s, h->stream, h->per_cu[2]));
         if (pcc) TIMED(h, 3, launch_perc(m, d, s, h->stream));
     }
+    if (pcc && n > 0) h->mirror_stale = true;   // p and thr now change on the device
     m.sweep += (uint32_t)n;
     if (series && n > 0 && m.measured < m.sweep) {
         TIMED(h, 4, launch_measure(m, d, m.series + 2 * (size_t)(m.sweep - 1), h->stream));
@@ -550,7 +560,7 @@ int engine_variant(sw_lattice* h, int* variant)
 
 int batched_sweep(sw_lattice* h, int32_t n)
 {
-    int rc = sync_mirror(h);
+    int rc = refresh_mirror(h);
     if (rc) return rc;
     bool any_pcc = false, any_series = false;
     for (size_t r = 0; r < h->reps.size(); ++r) {

@@ -73,6 +73,7 @@ struct sw_lattice {
 namespace sw {
 int handle_sync(sw_lattice* h);
 int sync_mirror(sw_lattice* h);
+int refresh_mirror(sw_lattice* h);
 int push_desc(sw_lattice* h, int r);
 int ensure_capacity(sw_lattice* h, int r, uint64_t need);
 int plain_sweep(sw_lattice* h, int r, int32_t n);

@@ -113,6 +113,17 @@ def test_pcc_plain_matches_oracle_over_halvings():
         _check(lat, 0, spec, _oracle(spec, 40))
 
 
+def test_pcc_plain_trace_growth_keeps_device_p():
+    """Growing the series and PCC traces between sweep calls rewrites the replica's
+    descriptor; p and the bond threshold, which the feedback changed on the device,
+    must survive that rewrite."""
+    spec = dict(dim=2, L=40, seed=12, p_bond=0.5, pcc=True, dp0=0.02, halve_every=3, series_cap=4)
+    with swgpu.Lattice(_params(spec)) as lat:
+        for n in (3, 5, 9, 1):
+            lat.sweep(n)
+        _check(lat, 0, spec, _oracle(spec, 18))
+
+
 def test_pcc_resume_sets_p():
     spec = dict(dim=2, L=24, seed=8, p_bond=0.5, pcc=True, dp0=0.02, halve_every=6)
     ref = _oracle(spec, 10)
