@@ -221,18 +221,6 @@ __device__ __forceinline__ void lds_store(int* p, int v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// root of x without writing: safe while other threads replace parents by
-// roots (every value it can read is an ancestor of x)
-__device__ __forceinline__ int lds_root(const int* par, int x)
-{
-    int p = lds_load(&par[x]);
-    while (p != x) {
-        x = p;
-        p = lds_load(&par[x]);
-    }
-    return x;
-}
-
 // Union of the sets of a and b for the tile labelling: both chains are walked
 // together (one LDS round trip per step), the larger root is hooked under the
 // smaller with an atomic min (from the displaced parent again when another
@@ -669,26 +657,77 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
     // 4) tile-local labels (the cluster's tile root) of the part and of its
     //    face sites, and border flags: a cluster is a border cluster when one
     //    of its runs touches a near face or has an open link leaving through a
-    //    far face.  Every run start walks to its root once (read only: the
-    //    parents no longer change).
+    //    far face.  Every run start walks to its root once and stores it as
+    //    its parent (the parents only change by such stores now, each of
+    //    which writes an ancestor).  A thread keeps two walks in flight and
+    //    starts its next run start as soon as one ends, so a wave waits about
+    //    half as many LDS round trips as its busiest thread has steps.
+    const int rowk = r * C::TX;
+    const uint32_t ss16 = partok ? (uint32_t)(SS >> xp) & (uint32_t)low_bits(np) : 0u;   // run starts of the part
+    {
+        uint32_t pend = ss16;
+        int sa = -1, na = 0, sb = -1, nb = 0;   // start and current node of the two walks (-1: idle)
+        auto next = [&](int& st, int& nd) {
+            if (pend) {
+                st = rowk + xp + __builtin_ctz(pend);
+                pend &= pend - 1u;
+            } else {
+                st = -1;
+            }
+            nd = st < 0 ? 0 : st;
+        };
+        next(sa, na);
+        next(sb, nb);
+        while (__ballot(sa >= 0 || sb >= 0)) {
+            const int pa = lds_load(&sm.par[na]);   // idle walks read par[0], a root
+            const int pb = lds_load(&sm.par[nb]);
+            if (sa >= 0) {
+                if (pa != na) {
+                    na = pa;
+                } else {
+                    if (na != sa) lds_store(&sm.par[sa], na);
+                    next(sa, na);
+                }
+            }
+            if (sb >= 0) {
+                if (pb != nb) {
+                    nb = pb;
+                } else {
+                    if (nb != sb) lds_store(&sm.par[sb], nb);
+                    next(sb, nb);
+                }
+            }
+        }
+    }
+    wave_lds_sync();   // the run start before xp is a thread of the same row, so of this wave
     if (partok) {
         uint16_t* nearf = R.face + (size_t)t * (2 * C::FT);
         uint16_t* farf = nearf + C::FT;
-        const int rowk = r * C::TX;
         const bool nearrow = ly == 0 || (C::D == 3 && lz == 0);
         uint64_t cross = 0;                                   // open links leaving through the far y / z faces
         if (edgeY) cross |= opn[1];
         if (edgeZ) cross |= opn[C::D - 1];
         const int last = 63 - __clzll((long long)SS);
         const bool xout = (opn[0] >> (g.wx - 1)) & 1ull;
-        uint32_t cur = (uint32_t)lds_root(sm.par, rowk + start_at(SS, xp));
-        const uint32_t ss16 = (uint32_t)(SS >> xp) & (uint32_t)low_bits(np);   // run starts of the part
+        uint32_t rt[16];                                      // roots of the part's run starts
+        {
+            const uint4* pv = reinterpret_cast<const uint4*>(sm.par + rowk + xp);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint4 v = pv[k];
+                rt[4 * k] = v.x;
+                rt[4 * k + 1] = v.y;
+                rt[4 * k + 2] = v.z;
+                rt[4 * k + 3] = v.w;
+            }
+        }
+        uint32_t cur = (ss16 & 1u) ? rt[0] : (uint32_t)lds_load(&sm.par[rowk + start_at(SS, xp)]);
         uint32_t pk[8];
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             if ((ss16 >> j) & 1u) {
                 const int x = xp + j;
-                if (j > 0) cur = (uint32_t)lds_root(sm.par, rowk + x);
+                cur = rt[j];
                 bool b = nearrow || x == 0 || (x == last && xout);
                 if (!b && cross) {
                     const uint64_t later = SS & ~low_bits(x + 1);
@@ -765,6 +804,7 @@ constexpr uint32_t kK2Empty = 0xFFFFFFFFu;
 
 template <class C>
 struct K2Cfg {
+    static constexpr int NT = (C::FT <= 128) ? 128 : kBlock;   // threads per tile: about one per face site
     static constexpr int HBITS = (2 * C::FT <= 256) ? 8 : (2 * C::FT <= 512) ? 9 : (2 * C::FT <= 1024) ? 10
                                : (2 * C::FT <= 2048) ? 11 : 12;
     static constexpr int H = 1 << HBITS;   // hash slots: at least twice the face sites

@@ -477,7 +477,12 @@ int launch_k2(const SwRep& h, SwRep* d, hipStream_t stream)
 {
     const int grid = h.ntiles;
     switch (h.dim * 16 + h.shape) {
-#define L2(id, D, X, Y, Z) SW_LAUNCH_CASE(id, D, X, Y, Z, k2_kernel, d)
+#define L2(id, D, X, Y, Z)                                                                   \
+    case (D * 16 + id): {                                                                    \
+        using C = TileCfg<D, X, Y, Z>;                                                       \
+        hipLaunchKernelGGL(k2_kernel<C>, dim3(grid), dim3(K2Cfg<C>::NT), 0, stream, d);      \
+        break;                                                                               \
+    }
         SW_SHAPES(L2)
         default: return -1;
     }
