@@ -336,8 +336,10 @@ int sync_mirror(sw_lattice* h)
         SwRep& m = h->reps[i].h;
         m.thr = tmp[i].thr;
         m.p = tmp[i].p;
-        m.sweep = tmp[i].sweep;
-        m.measured = tmp[i].measured;
+        if (!h->reps[i].dev_count_stale) {
+            m.sweep = tmp[i].sweep;
+            m.measured = tmp[i].measured;
+        }
     }
     h->mirror_stale = false;
     return SW_OK;
@@ -356,6 +358,7 @@ int push_desc(sw_lattice* h, int r)
 {
     hipError_t e = hipMemcpyAsync(&h->d_reps[r], &h->reps[r].h, sizeof(SwRep), hipMemcpyHostToDevice, h->stream);
     if (e != hipSuccess) return hip_fail(e, "writing a replica descriptor");
+    h->reps[r].dev_count_stale = false;
     e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     return SW_OK;
@@ -502,7 +505,10 @@ int plain_sweep(sw_lattice* h, int r, int32_t n)
         m.measured = m.sweep;
     }
     if (n > 0) {
-        if (launch_set_state(d, m.sweep, m.measured, 0.0, 0, 0, h->stream)) return fail(SW_EHIP, "state update launch failed");
+        // the kernels of plain sweeps take the sweep index as an argument; the
+        // device copy of the counters is brought up to date before a batched
+        // sweep reads it
+        rep.dev_count_stale = true;
         rep.labels_valid = true;
     }
     return SW_OK;
@@ -562,6 +568,13 @@ int batched_sweep(sw_lattice* h, int32_t n)
 {
     int rc = refresh_mirror(h);
     if (rc) return rc;
+    for (auto& rep : h->reps) {
+        if (!rep.dev_count_stale) continue;
+        const SwRep& m = rep.h;
+        if (launch_set_state(&h->d_reps[&rep - h->reps.data()], m.sweep, m.measured, 0.0, 0, 0, h->stream))
+            return fail(SW_EHIP, "state update launch failed");
+        rep.dev_count_stale = false;
+    }
     bool any_pcc = false, any_series = false;
     for (size_t r = 0; r < h->reps.size(); ++r) {
         SwRep& m = h->reps[r].h;
@@ -867,6 +880,7 @@ int sw_set_spins(sw_lattice* h, int32_t replica, const int8_t* host_buf, int64_t
     h->reps[replica].labels_valid = false;
     if (launch_set_state(&h->d_reps[replica], m.sweep, m.measured, m.p, m.thr, pcc ? 1 : 0, h->stream))
         return fail(SW_EHIP, "state update launch failed");
+    h->reps[replica].dev_count_stale = false;
     return handle_sync(h);
 }
 

@@ -17,6 +17,7 @@ struct ReplicaH {
     SwRep h{};               // host mirror of the device descriptor
     bool own_spins = true;
     bool labels_valid = false;
+    bool dev_count_stale = false;   // plain sweeps advanced sweep / measured on the host only
 };
 
 struct TimedLaunch {
