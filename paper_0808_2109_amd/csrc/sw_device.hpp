@@ -71,7 +71,7 @@ struct SwRep {
     uint32_t* xbits;            // ntiles * xwords crossing-link bits
     uint32_t* fbits;            // ntiles * fbw: border roots of each tile (bit per tile-local site)
     uint16_t* face;             // ntiles * 2 * ft: labels of the near, then the far face sites
-    uint32_t* bflip;            // ntiles * fbw: flip bits of each tile's border roots (K3a -> K3b)
+    uint32_t* bflip;            // ntiles * fbw: flip bit of every tile-local root (K3a -> K3b)
     int64_t* series;            // 2 * series_cap
     int64_t* acc;               // 2 scratch accumulators (measure)
     uint64_t* cand;             // PCC: dim * N candidate marks (tag << 32 | ~slot)
@@ -553,7 +553,8 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
     if (active && q == 0) sm.S[r] = S;
     if (tid < 2) sm.XF[tid] = 0;
     for (int w = tid; w < C::FBW; w += blockDim.x) sm.FB[w] = 0;
-    for (int k = tid; k < C::TS; k += blockDim.x) sm.par[k] = k;
+    for (int k = 4 * tid; k < C::TS; k += 4 * (int)blockDim.x)
+        *reinterpret_cast<uint4*>(&sm.par[k]) = make_uint4((uint32_t)k, (uint32_t)k + 1u, (uint32_t)k + 2u, (uint32_t)k + 3u);
     __syncthreads();
 
     // 2) bonds of the row's own links (x, d), each thread those of its part
@@ -878,16 +879,20 @@ __device__ void k2_tile(const SwRep& R, int t, K2Smem<C>& sm)
 }
 
 // --------------------------------------------------------------------------
-// K3a: border roots, one wave per tile.  The roots in the tile's border
-// bitmap are compacted into a list; each lane takes one at a time, finds its
-// cluster root (the smallest site index of the cluster: the label identity
-// that the min-label rule of Sec. II.B converges to), keeps it as parent when
-// labels are written, and records the cluster's flip bit.
+// K3a: border roots and the tile's flip bitmap, one wave per tile.  The roots
+// in the tile's border bitmap are compacted into a list; each lane takes one
+// at a time, finds its cluster root (the smallest site index of the cluster:
+// the label identity that the min-label rule of Sec. II.B converges to),
+// keeps it as parent when labels are written, and records the cluster's flip
+// bit.  Each lane also draws the flip bits of one tile row: an interior root
+// is its own cluster's label, so its bit is the one drawn for its own site.
+// The result is one bit per tile-local site, meaningful at the tile roots.
 // --------------------------------------------------------------------------
 template <class C>
 struct K3aSmem {
     uint16_t list[2 * C::FT];    // the tile's border roots (each has a site on a face)
-    uint32_t BF[C::FBW];
+    uint32_t BF[C::FBW];         // flip bits of the border roots
+    uint32_t FBt[C::FBW];        // the border-root bitmap
     int cnt;
 };
 
@@ -899,11 +904,13 @@ __device__ void k3a_tile(const SwRep& R, int t, uint32_t s, K3aSmem<C>& sm)
     const TileGeo g = tile_geo<C>(R, t);
     const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
     const bool keep = R.lab32 != nullptr || (R.flags & FLAG_PCC) != 0;
+    static_assert(C::NR == 64, "one tile row per lane");
     if (lane == 0) sm.cnt = 0;
     for (int w = lane; w < C::FBW; w += 64) sm.BF[w] = 0;
     wave_lds_sync();
     for (int w = lane; w < C::FBW; w += 64) {
         uint32_t m = R.fbits[(size_t)t * C::FBW + w];
+        sm.FBt[w] = m;
         if (!m) continue;
         int pos = atomicAdd(&sm.cnt, __popc(m));
         while (m) {
@@ -914,6 +921,13 @@ __device__ void k3a_tile(const SwRep& R, int t, uint32_t s, K3aSmem<C>& sm)
         }
     }
     wave_lds_sync();
+    uint64_t rf = 0;   // flip bits of this lane's row
+    {
+        const int ly = lane % C::TY, lz = lane / C::TY;
+        if (ly < g.wy && lz < g.wz)
+            rf = row_flips((uint32_t)g.x0 + (uint32_t)R.L * ((uint32_t)(g.y0 + ly) + (uint32_t)R.L * (uint32_t)(g.z0 + lz)),
+                           g.wx, s, k0, k1);
+    }
     const int nb = sm.cnt;
     if (nb > CAP && lane == 0) flag_error(R, ERR_TILE_LABEL);   // more border roots than face sites
     for (int i = lane; i < min(nb, CAP); i += 64) {
@@ -928,20 +942,24 @@ __device__ void k3a_tile(const SwRep& R, int t, uint32_t s, K3aSmem<C>& sm)
         if (flip_bit(root, s, k0, k1)) atomicOr(&sm.BF[lr >> 5], 1u << (lr & 31u));
     }
     wave_lds_sync();
-    for (int w = lane; w < C::FBW; w += 64) R.bflip[(size_t)t * C::FBW + w] = sm.BF[w];
+    constexpr int WPR = C::TX / 32;   // bitmap words per row
+#pragma unroll
+    for (int k = 0; k < WPR; ++k) {
+        const int w = lane * WPR + k;
+        const uint32_t fb = sm.FBt[w];
+        R.bflip[(size_t)t * C::FBW + w] = (fb & sm.BF[w]) | (~fb & (uint32_t)(rf >> (32 * k)));
+    }
 }
 
 // --------------------------------------------------------------------------
-// K3b: cluster flip.  A border root's flip bit comes from K3a; an interior
-// root is its own cluster label and takes its flip bit from the tile's own
-// rows of flip bits.  Every site gets its cluster's new spin.  Optionally
-// writes the final labels and marks percolation coverage (PCC).
+// K3b: cluster flip.  Every site takes the flip bit that K3a recorded for its
+// tile root and gets its cluster's new spin.  Optionally writes the final
+// labels and marks percolation coverage (PCC).
 // --------------------------------------------------------------------------
 template <class C>
 struct K3Smem {
-    uint64_t RF[C::NR];          // flip bits of the tile's own sites, one mask per row
-    uint32_t BF[C::FBW];         // flip bits of the tile's border roots
-    uint32_t FBt[C::FBW];        // the tile's border-root bitmap
+    uint32_t FL[C::FBW];         // flip bit of every tile root (from K3a)
+    uint32_t FBt[C::FBW];        // the tile's border-root bitmap (labels and PCC only)
     uint32_t wor[kK3Block / 64]; // per-wave word for combining coverage marks
 };
 
@@ -1009,9 +1027,9 @@ __device__ __forceinline__ uint32_t k3_site(const SwRep& R, const K3Smem<C>& sm,
         flag_error(R, ERR_TILE_LABEL);
         return 0xFFu;
     }
-    const bool border = (sm.FBt[lr >> 5] >> (lr & 31u)) & 1u;
-    const uint32_t bit = border ? (sm.BF[lr >> 5] >> (lr & 31u)) & 1u : (uint32_t)(sm.RF[lr / C::TX] >> (lr % C::TX)) & 1u;
+    const uint32_t bit = (sm.FL[lr >> 5] >> (lr & 31u)) & 1u;
     if (labels || pcc) {
+        const bool border = (sm.FBt[lr >> 5] >> (lr & 31u)) & 1u;
         uint32_t root = local_to_global<C>(lr, g.x0, g.y0, g.z0, R.L);
         if (border) root = (uint32_t)R.par[root];   // set to the cluster root by K3a
         if (root >= R.N) {
@@ -1030,7 +1048,6 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
     const int tid = threadIdx.x;
     const TileGeo g = tile_geo<C>(R, t);
     const uint32_t L = (uint32_t)R.L;
-    const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
     const bool labels = R.lab32 != nullptr;
     const bool pcc = (R.flags & FLAG_PCC) != 0;
     constexpr int QR = C::TX / 4;                       // quads of sites per row
@@ -1038,7 +1055,7 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
     const bool quads = (L & 3u) == 0;                   // then every row and the tile width are multiples of 4
 
     // 0) the tile's labels, four sites per thread and load, issued first so
-    //    that they arrive while the row flip bits are drawn
+    //    that they arrive while the flip bitmap is staged
     uint2 lv[QPT];
 #pragma unroll
     for (int j = 0; j < QPT; ++j) {
@@ -1051,19 +1068,12 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
                                                     L * ((uint32_t)(g.y0 + ly) + L * (uint32_t)(g.z0 + lz)));
     }
 
-    // 1) the tile's border bitmap and their flip bits (from K3a); the flip
-    //    bits of its own rows
+    // 1) the tile's flip bitmap (from K3a), and its border bitmap when the
+    //    cluster roots are needed
     if (tid < kK3Block / 64) sm.wor[tid] = 0;
     for (int w = tid; w < C::FBW; w += blockDim.x) {
-        sm.FBt[w] = R.fbits[(size_t)t * C::FBW + w];
-        sm.BF[w] = R.bflip[(size_t)t * C::FBW + w];
-    }
-    if (tid < C::NR) {
-        const int ly = tid % C::TY, lz = tid / C::TY;
-        uint64_t rf = 0;
-        if (ly < g.wy && lz < g.wz)
-            rf = row_flips((uint32_t)g.x0 + L * ((uint32_t)(g.y0 + ly) + L * (uint32_t)(g.z0 + lz)), g.wx, s, k0, k1);
-        sm.RF[tid] = rf;
+        sm.FL[w] = R.bflip[(size_t)t * C::FBW + w];
+        if (labels || pcc) sm.FBt[w] = R.fbits[(size_t)t * C::FBW + w];
     }
     __syncthreads();
 
