@@ -315,6 +315,23 @@ __device__ __forceinline__ uint32_t ro_find(const SwRep& R, uint32_t x)
     return x;
 }
 
+// ro_find of a and b, the two chains walked together (one round trip per
+// step of the longer one)
+__device__ __forceinline__ void ro_find2(const SwRep& R, uint32_t& a, uint32_t& b)
+{
+    int pa = R.par[a], pb = R.par[b];
+    while ((uint32_t)pa != a || (uint32_t)pb != b) {
+        if (pa < 0 || (uint32_t)pa > a || pb < 0 || (uint32_t)pb > b) {
+            flag_error(R, ERR_PARENT);
+            return;
+        }
+        a = (uint32_t)pa;
+        b = (uint32_t)pb;
+        pa = R.par[a];
+        pb = R.par[b];
+    }
+}
+
 // --------------------------------------------------------------------------
 // Bit tools.
 // --------------------------------------------------------------------------
@@ -772,13 +789,13 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
 
     // 5) the border bitmap and the far x face's crossing bits; every border
     //    root starts its own tree in the global union-find
-    for (int w = tid; w < C::FBW; w += blockDim.x) {
-        uint32_t m = sm.FB[w];
-        R.fbits[(size_t)t * C::FBW + w] = m;
+    for (int w = tid; w < C::FBW; w += blockDim.x) R.fbits[(size_t)t * C::FBW + w] = sm.FB[w];
+    for (int hw = tid; hw < 2 * C::FBW; hw += blockDim.x) {   // 16 bits per thread
+        uint32_t m = (sm.FB[hw >> 1] >> (16 * (hw & 1))) & 0xFFFFu;
         while (m) {
             const int b = __ffs(m) - 1;
             m &= m - 1u;
-            const uint32_t gi = local_to_global<C>((uint32_t)(w * 32 + b), g.x0, g.y0, g.z0, (int)L);
+            const uint32_t gi = local_to_global<C>((uint32_t)(hw * 16 + b), g.x0, g.y0, g.z0, (int)L);
             R.par[gi] = (int32_t)gi;
         }
     }
@@ -930,16 +947,28 @@ __device__ void k3a_tile(const SwRep& R, int t, uint32_t s, K3aSmem<C>& sm)
     }
     const int nb = sm.cnt;
     if (nb > CAP && lane == 0) flag_error(R, ERR_TILE_LABEL);   // more border roots than face sites
-    for (int i = lane; i < min(nb, CAP); i += 64) {
-        const uint32_t lr = sm.list[i];
-        const uint32_t gi = local_to_global<C>(lr, g.x0, g.y0, g.z0, R.L);
-        if (gi >= R.N) {
+    const int nl = min(nb, CAP);
+    // two list entries per lane and step (i and i + 64), their finds together
+    for (int i = lane; i < nl; i += 128) {
+        const bool two = i + 64 < nl;
+        uint32_t lr[2], gi[2], root[2];
+        lr[0] = sm.list[i];
+        lr[1] = two ? sm.list[i + 64] : lr[0];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) gi[e] = local_to_global<C>(lr[e], g.x0, g.y0, g.z0, R.L);
+        if (gi[0] >= R.N || gi[1] >= R.N) {
             flag_error(R, ERR_TILE_LABEL);
             continue;
         }
-        const uint32_t root = ro_find(R, gi);
-        if (keep && root != gi) R.par[gi] = (int32_t)root;
-        if (flip_bit(root, s, k0, k1)) atomicOr(&sm.BF[lr >> 5], 1u << (lr & 31u));
+        root[0] = gi[0];
+        root[1] = gi[1];
+        ro_find2(R, root[0], root[1]);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            if (e == 1 && !two) break;
+            if (keep && root[e] != gi[e]) R.par[gi[e]] = (int32_t)root[e];
+            if (flip_bit(root[e], s, k0, k1)) atomicOr(&sm.BF[lr[e] >> 5], 1u << (lr[e] & 31u));
+        }
     }
     wave_lds_sync();
     constexpr int WPR = C::TX / 32;   // bitmap words per row
