@@ -82,9 +82,15 @@ __device__ __forceinline__ int xcd_item(int nitems)
     return i0;
 }
 
+// waves per SIMD asked of the compiler for K1: 64-wide tiles (four-wave
+// workgroups) gain from an eighth wave even with scalar registers spilled to
+// vector lanes; 32-wide tiles (two-wave workgroups) run better at fewer
 template <class C>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void k1_kernel(const SwRep* Rd,
-                                                                                           uint32_t s, int64_t* em)
+constexpr int k1_waves() { return C::TX == 64 ? 8 : 6; }
+
+template <class C>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(k1_waves<C>()))) void k1_kernel(
+    const SwRep* Rd, uint32_t s, int64_t* em)
 {
     __shared__ K1Smem<C> sm;
     const SwRep R = *Rd;
