@@ -33,7 +33,9 @@
  *     A device buffer bound with sw_bind_device_spins stays the caller's.
  *   - Streams: `hip_stream` is a hipStream_t passed as void* (NULL: the handle
  *     creates and owns a stream).  Sweeps are enqueued asynchronously; every
- *     sw_get_* / sw_measure call synchronises the handle's stream.
+ *     sw_get_* / sw_measure call synchronises the handle's stream and checks
+ *     the device consistency word, so a failure detected on the device during
+ *     sweeps is returned (SW_EHIP) by the next such call.
  *   - Handles are not thread-safe; a server serialises its own calls.
  */
 #ifndef SW_API_H
