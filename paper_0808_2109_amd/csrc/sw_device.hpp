@@ -817,12 +817,18 @@ __device__ __forceinline__ uint32_t tile_site_global(const SwRep& R, int ix, int
 // K2 works one tile per workgroup.  Many open links across a face join the
 // same two tile-local clusters; every distinct (face, near label, far label)
 // triple is entered in an LDS hash set and only its first link makes the
-// global union.
+// global union.  The work goes in three steps: the crossing bits are staged
+// in LDS; each thread issues the label loads of all its face sites at once
+// and enters its open links in the set, the first link of each triple going
+// to a compact list; the unions of the list are then spread over all
+// threads, so that a thread waits for about one union instead of one per
+// face site it owns.
 constexpr uint32_t kK2Empty = 0xFFFFFFFFu;
 
 template <class C>
 struct K2Cfg {
     static constexpr int NT = (C::FT <= 128) ? 128 : kBlock;   // threads per tile: about one per face site
+    static constexpr int KF = (C::FT + NT - 1) / NT;           // face sites per thread (blockDim >= NT)
     static constexpr int HBITS = (2 * C::FT <= 256) ? 8 : (2 * C::FT <= 512) ? 9 : (2 * C::FT <= 1024) ? 10
                                : (2 * C::FT <= 2048) ? 11 : 12;
     static constexpr int H = 1 << HBITS;   // hash slots: at least twice the face sites
@@ -832,6 +838,9 @@ struct K2Cfg {
 template <class C>
 struct K2Smem {
     uint32_t keys[K2Cfg<C>::H];
+    uint32_t list[C::FT];      // keys of the unions to make (at most one per face site)
+    uint32_t xb[C::XW];        // the tile's crossing bits
+    int cnt;
 };
 
 // true for the first caller with this key (keys < 2^28; the set is never full)
@@ -848,44 +857,87 @@ __device__ __forceinline__ bool k2_first(K2Smem<C>& sm, uint32_t key)
     }
 }
 
+// face set (0 x, 1 y, 2 z) of far-face index f, its index within the set
+// and the first crossing-bit word of the set
+template <class C>
+__device__ __forceinline__ void k2_face(int f, int& d, int& fb, int& wbase)
+{
+    if (f < C::F0) {
+        d = 0;
+        fb = f;
+        wbase = 0;
+    } else if (f < C::F0 + C::F1) {
+        d = 1;
+        fb = f - C::F0;
+        wbase = C::W0;
+    } else {
+        d = 2;
+        fb = f - C::F0 - C::F1;
+        wbase = C::W0 + C::W1;
+    }
+}
+
 template <class C>
 __device__ void k2_tile(const SwRep& R, int t, K2Smem<C>& sm)
 {
-    const int tid = threadIdx.x;
-    for (int i = tid; i < K2Cfg<C>::H; i += blockDim.x) sm.keys[i] = kK2Empty;
+    using K = K2Cfg<C>;
+    const int tid = threadIdx.x, nt = (int)blockDim.x;
+    for (int i = tid; i < K::H; i += nt) sm.keys[i] = kK2Empty;
+    for (int i = tid; i < C::XW; i += nt) sm.xb[i] = R.xbits[(size_t)t * C::XW + i];
+    if (tid == 0) sm.cnt = 0;
     __syncthreads();
-    const uint32_t* xb = R.xbits + (size_t)t * C::XW;
     const int ix = t % R.ntx, iy = (t / R.ntx) % R.nty, iz = t / (R.ntx * R.nty);
     const uint16_t* farf = R.face + (size_t)t * (2 * C::FT) + C::FT;
-    for (int f = tid; f < C::FT; f += blockDim.x) {
-        int d, fb, wbase;
-        if (f < C::F0) {
-            d = 0;
-            fb = f;
-            wbase = 0;
-        } else if (f < C::F0 + C::F1) {
-            d = 1;
-            fb = f - C::F0;
-            wbase = C::W0;
-        } else {
-            d = 2;
-            fb = f - C::F0 - C::F1;
-            wbase = C::W0 + C::W1;
+    // 1) the labels at both ends of every open link of this thread's face sites
+    uint32_t la[K::KF], lb[K::KF];
+    int dk[K::KF];
+    bool open[K::KF];
+#pragma unroll
+    for (int k = 0; k < K::KF; ++k) {
+        const int f = tid + k * nt;
+        open[k] = false;
+        dk[k] = 0;
+        la[k] = lb[k] = 0u;
+        if (f < C::FT) {
+            int d, fb, wbase;
+            k2_face<C>(f, d, fb, wbase);
+            dk[k] = d;
+            open[k] = (sm.xb[wbase + (fb >> 5)] >> (fb & 31)) & 1u;
         }
-        if (!((xb[wbase + (fb >> 5)] >> (fb & 31)) & 1u)) continue;
+        if (open[k]) {
+            int jx = ix, jy = iy, jz = iz;
+            if (dk[k] == 0) jx = (ix + 1 == R.ntx) ? 0 : ix + 1;
+            else if (dk[k] == 1) jy = (iy + 1 == R.nty) ? 0 : iy + 1;
+            else jz = (iz + 1 == R.ntz) ? 0 : iz + 1;
+            const int tn = jx + R.ntx * (jy + R.nty * jz);
+            la[k] = farf[f];
+            lb[k] = R.face[(size_t)tn * (2 * C::FT) + f];
+        }
+    }
+    // 2) the first link of each (face, near label, far label) triple
+#pragma unroll
+    for (int k = 0; k < K::KF; ++k) {
+        if (!open[k]) continue;
+        if (la[k] >= (uint32_t)C::TS || lb[k] >= (uint32_t)C::TS) {
+            flag_error(R, ERR_TILE_LABEL);
+            continue;
+        }
+        const uint32_t key = la[k] | (lb[k] << 13) | ((uint32_t)dk[k] << 26);
+        if (k2_first<C>(sm, key)) sm.list[atomicAdd(&sm.cnt, 1)] = key;
+    }
+    __syncthreads();
+    // 3) the unions, spread over the workgroup
+    const int n = sm.cnt;
+    for (int i = tid; i < n; i += nt) {
+        const uint32_t key = sm.list[i];
+        const uint32_t la0 = key & 0x1FFFu, lb0 = (key >> 13) & 0x1FFFu;
+        const int d = (int)(key >> 26);
         int jx = ix, jy = iy, jz = iz;
         if (d == 0) jx = (ix + 1 == R.ntx) ? 0 : ix + 1;
         else if (d == 1) jy = (iy + 1 == R.nty) ? 0 : iy + 1;
         else jz = (iz + 1 == R.ntz) ? 0 : iz + 1;
-        const int tn = jx + R.ntx * (jy + R.nty * jz);
-        const uint32_t la = farf[f], lb = R.face[(size_t)tn * (2 * C::FT) + f];
-        if (la >= (uint32_t)C::TS || lb >= (uint32_t)C::TS) {
-            flag_error(R, ERR_TILE_LABEL);
-            continue;
-        }
-        if (!k2_first<C>(sm, la | (lb << 13) | ((uint32_t)d << 26))) continue;
-        const uint32_t ra = tile_site_global<C>(R, ix, iy, iz, la);
-        const uint32_t rb = tile_site_global<C>(R, jx, jy, jz, lb);
+        const uint32_t ra = tile_site_global<C>(R, ix, iy, iz, la0);
+        const uint32_t rb = tile_site_global<C>(R, jx, jy, jz, lb0);
         if (ra >= R.N || rb >= R.N) {
             flag_error(R, ERR_TILE_LABEL);
             continue;
