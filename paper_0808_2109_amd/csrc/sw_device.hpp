@@ -827,7 +827,7 @@ constexpr uint32_t kK2Empty = 0xFFFFFFFFu;
 
 template <class C>
 struct K2Cfg {
-    static constexpr int NT = (C::FT <= 128) ? 128 : kBlock;   // threads per tile: about one per face site
+    static constexpr int NT = (C::FT <= 128) ? 64 : kBlock;    // threads per tile: one wave when the far faces are small (more tiles in flight)
     static constexpr int KF = (C::FT + NT - 1) / NT;           // face sites per thread (blockDim >= NT)
     static constexpr int HBITS = (2 * C::FT <= 256) ? 8 : (2 * C::FT <= 512) ? 9 : (2 * C::FT <= 1024) ? 10
                                : (2 * C::FT <= 2048) ? 11 : 12;
