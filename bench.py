@@ -289,11 +289,11 @@ def run_pcc(swgpu, workloads, sweeps: int):
             "p_c_fk_2d": 1.0 - 1.0 / (1.0 + 2.0 ** 0.5)}
 
 
-def run_serving(swgpu, workloads, n_jobs: int, budget_gib: float, slots: int, tick: int):
-    """Open-loop Poisson job stream through the continuous-batching server."""
+def run_serving(swgpu, workloads, n_jobs: int, budget_gib: float, slots: int, tick: int, rate: float = 50.0):
+    """Open-loop Poisson job stream (rate jobs/s) through the continuous-batching server."""
     import torch
 
-    jobs = workloads.serving(n_jobs=n_jobs)
+    jobs = workloads.serving(n_jobs=n_jobs, rate=rate)
     stream = torch.cuda.Stream()
     srv = swgpu.Server(int(budget_gib * (1 << 30)), max_slots=slots, sweeps_per_tick=tick,
                        stream=ctypes.c_void_p(stream.cuda_stream))
@@ -328,7 +328,7 @@ def run_serving(swgpu, workloads, n_jobs: int, budget_gib: float, slots: int, ti
     def pct(q):
         return lat[min(len(lat) - 1, int(q * len(lat)))] if lat else None
 
-    return {"jobs": n_jobs, "done": st["done"], "rejected": st["rejected"], "rate_per_s": 50.0,
+    return {"jobs": n_jobs, "done": st["done"], "rejected": st["rejected"], "rate_per_s": rate,
             "seconds": wall, "site_updates": st["site_updates"], "site_updates_per_s": st["site_updates"] / wall,
             "p50_latency_s": pct(0.5), "p99_latency_s": pct(0.99), "hbm_budget_gib": budget_gib,
             "slots": slots, "sweeps_per_tick": tick}
@@ -350,6 +350,9 @@ def main():
     ap.add_argument("--serving-jobs", type=int, default=40)
     ap.add_argument("--serving-budget-gib", type=float, default=64.0)
     ap.add_argument("--serving-slots", type=int, default=64)
+    ap.add_argument("--serving-load", type=float, default=None,
+                    help="with --serving: run the same jobs again with arrivals scaled so that the offered load is "
+                         "this fraction of the throughput the first (saturated) run measured")
     ap.add_argument("--serving-tick", type=int, default=25)
     ap.add_argument("--summarize", metavar="PROF_DIR",
                     help="write the profiles/ summaries from rocprofv3 runs under PROF_DIR (no GPU needed)")
@@ -457,6 +460,19 @@ def main():
     if args.serving:
         result["serving"] = run_serving(swgpu, workloads, args.serving_jobs, args.serving_budget_gib,
                                         args.serving_slots, args.serving_tick)
+        if args.serving_load:
+            # same jobs (the generator draws the same numbers at any rate), arrivals
+            # spaced so that the offered site-updates/s is the asked fraction of capacity
+            cap = result["serving"]["site_updates_per_s"]
+            jobs = workloads.serving(n_jobs=args.serving_jobs)
+            work = sum(j.replica.nsites * j.sweeps for j in jobs) / len(jobs)
+            rate = args.serving_load * cap / work
+            log(f"serving at {args.serving_load:.0%} of {cap:.3e} site-updates/s: {rate:.3f} jobs/s")
+            res = run_serving(swgpu, workloads, args.serving_jobs, args.serving_budget_gib, args.serving_slots,
+                              args.serving_tick, rate=rate)
+            res.update({"load": args.serving_load, "capacity_site_updates_per_s": cap,
+                        "mean_site_updates_per_job": work})
+            result["serving_at_load"] = res
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
         result["cpu_baseline"] = cpu_baseline(wl)
