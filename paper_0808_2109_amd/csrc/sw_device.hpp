@@ -1123,6 +1123,52 @@ __device__ __forceinline__ uint32_t k3_site(const SwRep& R, const K3Smem<C>& sm,
     return bit ? 0x01u : 0xFFu;
 }
 
+// K3b when neither final labels nor PCC marks are asked for and rows are
+// whole quads of sites (the plain sweep): labels in, spins out, one bitmap
+// word per site; the label check (a tile root precedes its sites) is folded
+// into one flag per thread
+template <class C>
+__device__ void k3_lean_tile(const SwRep& R, int t, const TileGeo& g, K3Smem<C>& sm)
+{
+    const int tid = threadIdx.x;
+    const uint32_t L = (uint32_t)R.L;
+    constexpr int QR = C::TX / 4;                       // quads of sites per row
+    constexpr int QPT = C::TS / 4 / kK3Block;           // quads per thread (blockDim = kK3Block)
+    static_assert((C::TS & (C::TS - 1)) == 0, "a label masked to TS - 1 stays inside the bitmap");
+    uint2 lv[QPT];
+    uint32_t gq[QPT];
+    bool ok[QPT];
+#pragma unroll
+    for (int j = 0; j < QPT; ++j) {
+        const int qd = tid + kK3Block * j;
+        const int r = qd / QR, xq = (qd % QR) * 4;
+        const int ly = r % C::TY, lz = r / C::TY;
+        ok[j] = ly < g.wy && lz < g.wz && xq < g.wx;
+        gq[j] = (uint32_t)(g.x0 + xq) + L * ((uint32_t)(g.y0 + ly) + L * (uint32_t)(g.z0 + lz));
+        lv[j] = ok[j] ? *reinterpret_cast<const uint2*>(R.lab16 + gq[j]) : make_uint2(0u, 0u);
+    }
+    for (int w = tid; w < C::FBW; w += blockDim.x) sm.FL[w] = R.bflip[(size_t)t * C::FBW + w];
+    __syncthreads();
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < QPT; ++j) {
+        const int qd = tid + kK3Block * j;
+        const uint32_t k = (uint32_t)((qd / QR) * C::TX + (qd % QR) * 4);
+        const uint32_t lab[4] = {lv[j].x & 0xFFFFu, lv[j].x >> 16, lv[j].y & 0xFFFFu, lv[j].y >> 16};
+        uint32_t out = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            bad |= lab[i] > k + (uint32_t)i;
+            const uint32_t lr = lab[i] & (uint32_t)(C::TS - 1);
+            const uint32_t bit = (sm.FL[lr >> 5] >> (lr & 31u)) & 1u;
+            out |= (bit ? 0x01u : 0xFFu) << (8 * i);
+        }
+        if (ok[j]) *reinterpret_cast<uint32_t*>(R.spins + gq[j]) = out;
+    }
+    if (bad) flag_error(R, ERR_TILE_LABEL);
+    __syncthreads();
+}
+
 template <class C>
 __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
 {
@@ -1134,6 +1180,10 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
     constexpr int QR = C::TX / 4;                       // quads of sites per row
     constexpr int QPT = C::TS / 4 / kK3Block;           // quads per thread (blockDim = kK3Block)
     const bool quads = (L & 3u) == 0;                   // then every row and the tile width are multiples of 4
+    if (!labels && !pcc && quads) {
+        k3_lean_tile<C>(R, t, g, sm);
+        return;
+    }
 
     // 0) the tile's labels, four sites per thread and load, issued first so
     //    that they arrive while the flip bitmap is staged

@@ -164,6 +164,23 @@ def test_full_size_first_sweeps(dim, L, T):
         _step_compare(lat, dim, L, seed, thr, spins, 2)
 
 
+@pytest.mark.parametrize("dim,L,T,shape", [(2, 8192, TC, 0), (3, 256, workloads.TC_3D, 0),
+                                           (3, 256, workloads.TC_3D, 1)])
+def test_full_size_bench_configuration(dim, L, T, shape):
+    """The lattices as the plain benchmark runs them (no series, no labels: the
+    flip kernel's lean path), in each tile shape its autotuner picks from:
+    spins after each of two sweeps, every site compared."""
+    seed = 1
+    with swgpu.Lattice(swgpu.make_params(dim, L, T=T, seed=seed)) as lat:
+        lat.set_tile_shape(0, shape)
+        thr = lat.state()[2]
+        spins = oracle.init_spins(dim, L, seed)
+        for k in range(2):
+            lat.sweep(1)
+            spins, _ = oracle.sweep(dim, L, seed, k, thr, spins)
+            assert np.array_equal(lat.spins(), spins), f"spins differ after sweep {k} (dim={dim} L={L} shape={shape})"
+
+
 def test_plain_full_size_later_sweep_properties():
     """8192^2 after 20 sweeps: properties that hold for any correct sweep.
 
