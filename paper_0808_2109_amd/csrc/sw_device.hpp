@@ -475,31 +475,13 @@ __device__ __forceinline__ uint64_t row_gather(uint32_t part, int q)
 
 // open bonds among the n <= 16 links lbase + x whose ends are equal (eq):
 // byte a of Philox(l >> 4, 0, s, BOND) for link l is the high byte of u; a tie
-// with thr >> 24 draws the low 24 bits.  `aligned` when lbase is a multiple
-// of 16 and n = 16: then one block holds all of them.
-__device__ inline uint32_t part_bonds(uint32_t eq, uint32_t lbase, int n, bool aligned, uint32_t s, uint32_t t_hi,
-                               uint32_t t_lo, uint32_t k0, uint32_t k1)
+// with thr >> 24 draws the low 24 bits from REFINE.  The general form, for
+// parts that do not start on a 16-link boundary (L not a multiple of 16).
+__device__ inline uint32_t part_bonds(uint32_t eq, uint32_t lbase, int n, uint32_t s, uint32_t t_hi, uint32_t t_lo,
+                                      uint32_t k0, uint32_t k1)
 {
     if (!eq) return 0;
     if (t_hi >= 256u) return eq;                     // P = 1: every equal link is a bond
-    if (aligned) {
-        const uint32_t y4 = t_hi * 0x01010101u;
-        const uint32_t blk = lbase >> 4;
-        const U4 q = philox10(blk, 0u, s, kTagBond, k0, k1);
-        uint32_t bits = nibbles4(bytes_lt(q.x, y4), bytes_lt(q.y, y4), bytes_lt(q.z, y4), bytes_lt(q.w, y4)) & eq;
-        // a byte equal to thr >> 24 (1 in 256 links) needs the low 24 bits
-        if (!(has_zero_byte(q.x ^ y4) | has_zero_byte(q.y ^ y4) | has_zero_byte(q.z ^ y4) | has_zero_byte(q.w ^ y4)))
-            return bits;
-        uint32_t ties = nibbles4(bytes_eq(q.x, y4), bytes_eq(q.y, y4), bytes_eq(q.z, y4), bytes_eq(q.w, y4)) & eq;
-        while (ties) {
-            const int k = __ffs(ties) - 1;
-            ties &= ties - 1u;
-            const uint32_t l = blk * 16u + (uint32_t)k;
-            const U4 q2 = philox10(l >> 2, 0u, s, kTagRefine, k0, k1);
-            if ((pick(q2, l & 3u) & 0xFFFFFFu) < t_lo) bits |= 1u << k;
-        }
-        return bits;
-    }
     uint32_t op = 0;
     const uint32_t b0 = lbase >> 4, b1 = (lbase + (uint32_t)n - 1u) >> 4;
     for (uint32_t blk = b0; blk <= b1; ++blk) {
@@ -518,6 +500,25 @@ __device__ inline uint32_t part_bonds(uint32_t eq, uint32_t lbase, int n, bool a
         }
     }
     return op;
+}
+
+// First stage of part_bonds for an aligned part: the bonds that the high
+// bytes decide, and in `ties` the equal links whose byte equals thr >> 24
+// (decided by the REFINE stream; the caller draws those for all directions
+// in one loop, so a wave pays about one refinement call per sweep instead of
+// one per direction)
+__device__ __forceinline__ uint32_t part_bonds_coarse(uint32_t eq, uint32_t lbase, uint32_t s, uint32_t t_hi,
+                                                      uint32_t k0, uint32_t k1, uint32_t& ties)
+{
+    ties = 0;
+    if (!eq) return 0;
+    if (t_hi >= 256u) return eq;                     // P = 1: every equal link is a bond
+    const uint32_t y4 = t_hi * 0x01010101u;
+    const U4 q = philox10(lbase >> 4, 0u, s, kTagBond, k0, k1);
+    const uint32_t bits = nibbles4(bytes_lt(q.x, y4), bytes_lt(q.y, y4), bytes_lt(q.z, y4), bytes_lt(q.w, y4)) & eq;
+    if (has_zero_byte(q.x ^ y4) | has_zero_byte(q.y ^ y4) | has_zero_byte(q.z ^ y4) | has_zero_byte(q.w ^ y4))
+        ties = nibbles4(bytes_eq(q.x, y4), bytes_eq(q.y, y4), bytes_eq(q.z, y4), bytes_eq(q.w, y4)) & eq;
+    return bits;
 }
 
 // Threads beyond K1Cfg<C>::NT (a workgroup sized for a larger tile) take part
@@ -589,13 +590,30 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
         }
         const uint32_t t_hi = (uint32_t)(thr >> 24);
         const uint32_t t_lo = (uint32_t)(thr & 0xFFFFFFu);
+        uint32_t bits[3] = {0u, 0u, 0u};
+        uint64_t ties = 0;                                   // bit 16 d + j: link (xp + j, d) needs REFINE
 #pragma unroll
         for (int d = 0; d < C::D; ++d) {
-            const uint32_t bits = partok ? part_bonds((uint32_t)(eq[d] >> xp) & 0xFFFFu, (uint32_t)d * N + gi0 + (uint32_t)xp,
-                                                      np, wide, s, t_hi, t_lo, k0, k1)
-                                         : 0u;
-            opn[d] = row_gather<RQ>(bits, q);
+            const uint32_t eqp = (uint32_t)(eq[d] >> xp) & 0xFFFFu;
+            const uint32_t lbase = (uint32_t)d * N + gi0 + (uint32_t)xp;
+            if (partok && wide) {
+                uint32_t td;
+                bits[d] = part_bonds_coarse(eqp, lbase, s, t_hi, k0, k1, td);
+                ties |= (uint64_t)td << (16 * d);
+            } else if (partok) {
+                bits[d] = part_bonds(eqp, lbase, np, s, t_hi, t_lo, k0, k1);
+            }
         }
+        while (ties) {
+            const int b = __builtin_ctzll(ties);
+            ties &= ties - 1ull;
+            const int d = b >> 4, j = b & 15;
+            const uint32_t l = (uint32_t)d * N + gi0 + (uint32_t)(xp + j);
+            const U4 q2 = philox10(l >> 2, 0u, s, kTagRefine, k0, k1);
+            if ((pick(q2, l & 3u) & 0xFFFFFFu) < t_lo) bits[d] |= 1u << j;
+        }
+#pragma unroll
+        for (int d = 0; d < C::D; ++d) opn[d] = row_gather<RQ>(bits[d], q);
         if (measure && partok) {
             const uint64_t pm = low_bits(np) << xp;
             m_acc += 2 * (int)__popcll(S & pm) - np;         // __popcll is unsigned
