@@ -30,7 +30,7 @@ int launch_set_state(SwRep* d, uint32_t sweep, uint32_t measured, double p, uint
 // enqueue n sweeps of every active replica as batched phase launches (used
 // under stream capture to build the batch graph)
 int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, int nitems, int n_sweeps, int any_pcc,
-                 int any_series, int grid, hipStream_t stream);
+                 int any_series, int any_3d, int grid, hipStream_t stream);
 
 int shape_count(int dim);
 int shape_extents(int dim, int id, int* tx, int* ty, int* tz);

@@ -291,8 +291,8 @@ __device__ __forceinline__ void flush_em(int64_t e, int64_t m, int64_t* dst, int
 // threads as the larger of the two tiles needs), with E, M of the incoming
 // configuration added to the replica's series entry
 template <class C2, class C3>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))) void kb1_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
-                                                    int n_sweeps)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(k1_waves<C2>()))) void kb1_kernel(
+    SwRep* reps, const EngineItem* items, int nitems, int it, int n_sweeps)
 {
     __shared__ __align__(16) char smem[cmax2(sizeof(K1Smem<C2>), sizeof(K1Smem<C3>))];
     const int i = blockIdx.x;
@@ -575,7 +575,7 @@ int launch_set_state(SwRep* d, uint32_t sweep, uint32_t measured, double p, uint
 }
 
 int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, int nitems, int n_sweeps, int any_pcc,
-                 int any_series, int grid, hipStream_t stream)
+                 int any_series, int any_3d, int grid, hipStream_t stream)
 {
     const int rgrid = (nreps + kBlock - 1) / kBlock;
     switch (variant) {
@@ -583,7 +583,8 @@ int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, i
     case i:                                                                                                          \
         for (int it = 0; it < n_sweeps; ++it) {                                                                      \
             hipLaunchKernelGGL((kb1_kernel<C2, C3>), dim3(nitems), dim3(max(K1Cfg<C2>::NT, K1Cfg<C3>::NT)), 0, stream, reps, items, nitems, it, n_sweeps); \
-            hipLaunchKernelGGL((kb2_kernel<C2, C3>), dim3(nitems), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
+            hipLaunchKernelGGL((kb2_kernel<C2, C3>), dim3(nitems), dim3(any_3d ? kBlock : K2Cfg<C2>::NT), 0, stream,     \
+                               reps, items, nitems, it, n_sweeps);                                                   \
             hipLaunchKernelGGL((kb3a_kernel<C2, C3>), dim3(nitems), dim3(64), 0, stream, reps, items, nitems, it, n_sweeps); \
             if (any_pcc)                                                                                             \
                 hipLaunchKernelGGL((kbc_kernel<C2, C3>), dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \

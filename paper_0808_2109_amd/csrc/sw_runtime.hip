@@ -575,7 +575,7 @@ int batched_sweep(sw_lattice* h, int32_t n)
             return fail(SW_EHIP, "state update launch failed");
         rep.dev_count_stale = false;
     }
-    bool any_pcc = false, any_series = false;
+    bool any_pcc = false, any_series = false, any_3d = false;
     for (size_t r = 0; r < h->reps.size(); ++r) {
         SwRep& m = h->reps[r].h;
         if (!m.active) continue;
@@ -583,6 +583,7 @@ int batched_sweep(sw_lattice* h, int32_t n)
         if (rc) return rc;
         any_pcc = any_pcc || (m.flags & FLAG_PCC);
         any_series = any_series || (m.flags & FLAG_SERIES);
+        any_3d = any_3d || m.dim == 3;
     }
     if (h->items_dirty || !h->items) {
         rc = build_items(h);
@@ -595,13 +596,13 @@ int batched_sweep(sw_lattice* h, int32_t n)
     int grid = std::min(device_cu_count() * h->batch_per_cu, h->nitems);
     if (grid >= 8) grid -= grid % 8;
     if (grid < 1) grid = 1;
-    if (h->graph_n != n || h->graph_grid != grid || h->graph_flags != (int)(any_pcc * 2 + any_series) ||
+    if (h->graph_n != n || h->graph_grid != grid || h->graph_flags != (int)(any_3d * 4 + any_pcc * 2 + any_series) ||
         h->graph_variant != variant) {
         drop_graph(h);
         hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
         int lrc = launch_batch(variant, h->d_reps, (int)h->reps.size(), h->items, h->nitems, n, any_pcc, any_series,
-                               grid, h->stream);
+                               any_3d, grid, h->stream);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(h->stream, &g);
         if (lrc || e != hipSuccess || !g) {
@@ -616,7 +617,7 @@ int batched_sweep(sw_lattice* h, int32_t n)
         }
         h->graph_n = n;
         h->graph_grid = grid;
-        h->graph_flags = (int)(any_pcc * 2 + any_series);
+        h->graph_flags = (int)(any_3d * 4 + any_pcc * 2 + any_series);
         h->graph_variant = variant;
     }
     hipEvent_t ev;
