@@ -1114,6 +1114,54 @@ __device__ __forceinline__ void pcc_mark(const SwRep& R, uint32_t root, bool val
     }
 }
 
+// PCC coverage marks of a quad of sites (x .. x+3 of one row): the candidate
+// words of all four sites and axes are loaded together, and marks of an axis
+// that hit the same bitmap word (the quad shares its x word and its y, z) are
+// merged before the wave-combined atomics (all lanes of the wave call it)
+template <class C>
+__device__ __forceinline__ void pcc_quad(const SwRep& R, const uint32_t root[4], bool valid, uint32_t x, uint32_t y,
+                                         uint32_t z, uint64_t tag, uint32_t bw, uint32_t nslots, uint32_t* wscr)
+{
+    uint64_t c[C::D][4];
+#pragma unroll
+    for (int a = 0; a < C::D; ++a)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) c[a][i] = valid ? R.cand[(size_t)a * R.N + root[i]] : 0ull;
+#pragma unroll
+    for (int a = 0; a < C::D; ++a) {
+        uint32_t* word[4];
+        uint32_t bits[4];
+        bool pend[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            word[i] = nullptr;
+            bits[i] = 0u;
+            pend[i] = false;
+            if ((c[a][i] & 0xFFFFFFFF00000000ull) == tag) {
+                const uint32_t slot = ~(uint32_t)c[a][i];
+                if (slot < nslots) {
+                    const uint32_t crd = (a == 0) ? x + (uint32_t)i : (a == 1) ? y : z;
+                    word[i] = R.bmp + ((size_t)a * nslots + slot) * bw + (crd >> 5);
+                    bits[i] = 1u << (crd & 31u);
+                    pend[i] = true;
+                } else {
+                    flag_error(R, ERR_SLOT);
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 1; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < i; ++j)
+                if (pend[i] && pend[j] && word[i] == word[j]) {
+                    bits[j] |= bits[i];
+                    pend[i] = false;
+                }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) wave_or(word[i], bits[i], pend[i], wscr);
+    }
+}
+
 // new spin byte of the site with tile-local index k and stored label v;
 // writes the final label when asked for and returns the cluster root (for
 // the coverage marks)
@@ -1243,18 +1291,18 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
             const uint2 v = lv[j];
             const int k = r * C::TX + xq;
             uint32_t out = 0;
+            uint32_t root[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
             for (int i = 0; i < 4; ++i) {
-                uint32_t root = 0;
                 if (valid) {
                     const uint32_t vi = (i == 0) ? (v.x & 0xFFFFu) : (i == 1) ? (v.x >> 16) : (i == 2) ? (v.y & 0xFFFFu) : (v.y >> 16);
-                    out |= k3_site<C>(R, sm, g, vi, k + i, gi + (uint32_t)i, labels, pcc, root) << (8 * i);
-                }
-                if (pcc) {
-                    const uint32_t crd[3] = {(uint32_t)(g.x0 + xq + i), (uint32_t)(g.y0 + ly), (uint32_t)(g.z0 + lz)};
-                    pcc_mark<C>(R, root, valid, crd, tag, bw, nslots, wscr);
+                    out |= k3_site<C>(R, sm, g, vi, k + i, gi + (uint32_t)i, labels, pcc, root[i]) << (8 * i);
                 }
             }
             if (valid) *reinterpret_cast<uint32_t*>(R.spins + gi) = out;
+            if (pcc)
+                pcc_quad<C>(R, root, valid, (uint32_t)(g.x0 + xq), (uint32_t)(g.y0 + ly), (uint32_t)(g.z0 + lz), tag, bw,
+                            nslots, wscr);
         }
     } else {
         for (int k0 = 0; k0 < C::TS; k0 += kK3Block) {

@@ -135,7 +135,9 @@ __global__ __launch_bounds__(kBlock) void kcand_kernel(const SwRep* Rd, uint32_t
 }
 
 // coverage test of the candidates' bitmaps (slots [c0, c1) of every axis);
-// the bitmaps are cleared for the next sweep
+// the bitmaps are cleared for the next sweep.  One wave per slot: its lanes
+// read consecutive bitmap words, and a ballot tells whether every coordinate
+// is covered.
 __device__ void perc_chunk(const SwRep& R, uint32_t c0, uint32_t c1, int* local_flag)
 {
     const uint32_t L = (uint32_t)R.L;
@@ -143,17 +145,18 @@ __device__ void perc_chunk(const SwRep& R, uint32_t c0, uint32_t c1, int* local_
     const uint32_t nslots = (R.dim == 3) ? L * L : L;
     const uint32_t tailbits = L & 31u;
     const uint32_t tailmask = tailbits ? ((1u << tailbits) - 1u) : 0xFFFFFFFFu;
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int a = 0; a < R.dim; ++a) {
-        for (uint32_t c = c0 + threadIdx.x; c < c1; c += kBlock) {
+        for (uint32_t c = c0 + wave; c < c1; c += nw) {   // wave-uniform
             uint32_t* bm = R.bmp + ((size_t)a * nslots + c) * bw;
-            bool full = true;
-            for (uint32_t w = 0; w < bw; ++w) {
+            bool gap = false;                            // a coordinate of this lane's words is not covered
+            for (uint32_t w = lane; w < bw; w += 64u) {
                 const uint32_t v = bm[w];
-                const uint32_t want = (w == bw - 1) ? tailmask : 0xFFFFFFFFu;
-                full = full && ((v & want) == want);
+                const uint32_t want = (w == bw - 1u) ? tailmask : 0xFFFFFFFFu;
+                gap = gap || (v & want) != want;
                 if (v) bm[w] = 0;
             }
-            if (full) *local_flag = 1;
+            if (!__ballot(gap) && lane == 0) *local_flag = 1;
         }
     }
 }
