@@ -240,14 +240,21 @@ def run_batched(swgpu, workloads, sweeps_batched: int, sweeps_plain: int):
     params = [swgpu.params_from_replica(r) for r in wl.replicas]
     sites = sum(r.nsites for r in wl.replicas)
     out = {"replicas": len(params), "sites": sites}
+    # the timed sweeps run as calls of `chunk` sweeps, the way a driver loop
+    # calls sw_sweep; the first call of that size (untimed) captures the
+    # hipGraph that the timed calls replay
+    chunk = max(1, min(100, sweeps_batched))
     with swgpu.Lattice(params) as lat:
         lat.set_mode(swgpu.SW_MODE_BATCHED)
         lat.sweep(10)                       # warm-up: the tuner times the current state
         lat.autotune(sweeps=2)
-        lat.sweep(1)
+        lat.sweep(chunk)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        lat.sweep(sweeps_batched)
+        done = 0
+        while done < sweeps_batched:
+            lat.sweep(min(chunk, sweeps_batched - done))
+            done += min(chunk, sweeps_batched - done)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out["batched"] = {"site_updates_per_s": sites * sweeps_batched / dt, "sweeps": sweeps_batched,
@@ -272,12 +279,16 @@ def run_pcc(swgpu, workloads, sweeps: int):
     params = [swgpu.params_from_replica(r) for r in wl.replicas]
     sites = sum(r.nsites for r in wl.replicas)
     stream = torch.cuda.Stream()
+    chunk = max(1, min(100, sweeps))        # timed as calls of `chunk` sweeps; the warm-up call builds their graph
     with swgpu.Lattice(params, stream=ctypes.c_void_p(stream.cuda_stream)) as lat:
         lat.set_mode(swgpu.SW_MODE_BATCHED)
-        lat.sweep(10)
+        lat.sweep(chunk)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        lat.sweep(sweeps)
+        done = 0
+        while done < sweeps:
+            lat.sweep(min(chunk, sweeps - done))
+            done += min(chunk, sweeps - done)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         ps = [lat.state(r)[1] for r in range(len(params))]
