@@ -24,6 +24,7 @@
 // do not depend on the order of unions, the tile shape or the schedule: the
 // result is bit-identical to a sequential labelling.
 #pragma once
+#include <type_traits>
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -1190,46 +1191,57 @@ __device__ __forceinline__ uint32_t k3_site(const SwRep& R, const K3Smem<C>& sm,
 }
 
 // K3b when neither final labels nor PCC marks are asked for and rows are
-// whole quads of sites (the plain sweep): labels in, spins out, one bitmap
-// word per site; the label check (a tile root precedes its sites) is folded
-// into one flag per thread
-template <class C>
+// whole groups of W = 4 or 8 sites (the plain sweep): labels in, spins out,
+// one bitmap word per site, W sites per load and store; the label check (a
+// tile root precedes its sites) is folded into one flag per thread
+template <class C, int W>
 __device__ void k3_lean_tile(const SwRep& R, int t, const TileGeo& g, K3Smem<C>& sm)
 {
+    static_assert(W == 4 || W == 8, "groups of 4 or 8 sites");
+    using LabV = typename std::conditional<W == 8, uint4, uint2>::type;   // W 16-bit labels
+    using SpinV = typename std::conditional<W == 8, uint2, uint32_t>::type; // W spin bytes
     const int tid = threadIdx.x;
     const uint32_t L = (uint32_t)R.L;
-    constexpr int QR = C::TX / 4;                       // quads of sites per row
-    constexpr int QPT = C::TS / 4 / kK3Block;           // quads per thread (blockDim = kK3Block)
+    constexpr int GR = C::TX / W;                        // groups of sites per row
+    constexpr int GPT = C::TS / W / kK3Block;            // groups per thread (blockDim = kK3Block)
+    static_assert(C::TS % (W * kK3Block) == 0, "whole groups per thread");
     static_assert((C::TS & (C::TS - 1)) == 0, "a label masked to TS - 1 stays inside the bitmap");
-    uint2 lv[QPT];
-    uint32_t gq[QPT];
-    bool ok[QPT];
+    LabV lv[GPT];
+    uint32_t gq[GPT];
+    bool ok[GPT];
 #pragma unroll
-    for (int j = 0; j < QPT; ++j) {
+    for (int j = 0; j < GPT; ++j) {
         const int qd = tid + kK3Block * j;
-        const int r = qd / QR, xq = (qd % QR) * 4;
+        const int r = qd / GR, xq = (qd % GR) * W;
         const int ly = r % C::TY, lz = r / C::TY;
         ok[j] = ly < g.wy && lz < g.wz && xq < g.wx;
         gq[j] = (uint32_t)(g.x0 + xq) + L * ((uint32_t)(g.y0 + ly) + L * (uint32_t)(g.z0 + lz));
-        lv[j] = ok[j] ? *reinterpret_cast<const uint2*>(R.lab16 + gq[j]) : make_uint2(0u, 0u);
+        if (ok[j]) lv[j] = *reinterpret_cast<const LabV*>(R.lab16 + gq[j]);
+        else lv[j] = LabV{};
     }
     for (int w = tid; w < C::FBW; w += blockDim.x) sm.FL[w] = R.bflip[(size_t)t * C::FBW + w];
     __syncthreads();
     bool bad = false;
 #pragma unroll
-    for (int j = 0; j < QPT; ++j) {
+    for (int j = 0; j < GPT; ++j) {
         const int qd = tid + kK3Block * j;
-        const uint32_t k = (uint32_t)((qd / QR) * C::TX + (qd % QR) * 4);
-        const uint32_t lab[4] = {lv[j].x & 0xFFFFu, lv[j].x >> 16, lv[j].y & 0xFFFFu, lv[j].y >> 16};
-        uint32_t out = 0;
+        const uint32_t k = (uint32_t)((qd / GR) * C::TX + (qd % GR) * W);
+        const uint32_t* lw = reinterpret_cast<const uint32_t*>(&lv[j]);   // two labels per word
+        uint32_t out[W / 4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            bad |= lab[i] > k + (uint32_t)i;
-            const uint32_t lr = lab[i] & (uint32_t)(C::TS - 1);
-            const uint32_t bit = (sm.FL[lr >> 5] >> (lr & 31u)) & 1u;
-            out |= (bit ? 0x01u : 0xFFu) << (8 * i);
+        for (int h = 0; h < W / 4; ++h) {
+            out[h] = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int n = 4 * h + i;
+                const uint32_t lab = (n & 1) ? lw[n >> 1] >> 16 : lw[n >> 1] & 0xFFFFu;
+                bad |= lab > k + (uint32_t)n;
+                const uint32_t lr = lab & (uint32_t)(C::TS - 1);
+                const uint32_t bit = (sm.FL[lr >> 5] >> (lr & 31u)) & 1u;
+                out[h] |= (bit ? 0x01u : 0xFFu) << (8 * i);
+            }
         }
-        if (ok[j]) *reinterpret_cast<uint32_t*>(R.spins + gq[j]) = out;
+        if (ok[j]) *reinterpret_cast<SpinV*>(R.spins + gq[j]) = *reinterpret_cast<const SpinV*>(out);
     }
     if (bad) flag_error(R, ERR_TILE_LABEL);
     __syncthreads();
@@ -1247,7 +1259,8 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
     constexpr int QPT = C::TS / 4 / kK3Block;           // quads per thread (blockDim = kK3Block)
     const bool quads = (L & 3u) == 0;                   // then every row and the tile width are multiples of 4
     if (!labels && !pcc && quads) {
-        k3_lean_tile<C>(R, t, g, sm);
+        if ((L & 7u) == 0) k3_lean_tile<C, 8>(R, t, g, sm);
+        else k3_lean_tile<C, 4>(R, t, g, sm);
         return;
     }
 
