@@ -362,10 +362,10 @@ __device__ __forceinline__ uint32_t nibbles4(uint32_t a, uint32_t b, uint32_t c,
     return byte_msbs(a) | (byte_msbs(b) << 4) | (byte_msbs(c) << 8) | (byte_msbs(d) << 12);
 }
 
-// highest set bit of s at or below x (s has bit 0 set)
+// highest set bit of s at or below x, 0 <= x < 64 (s has bit 0 set)
 __device__ __forceinline__ int start_at(uint64_t s, int x)
 {
-    return 63 - __clzll((long long)(s & low_bits(x + 1)));
+    return 63 - __clzll((long long)(s & (~0ull >> (63 - x))));
 }
 
 // number of set bits of `mask` below this lane
