@@ -76,3 +76,13 @@ def test_tile_shapes_table(lib_path):
         for tx, ty, tz in shapes:
             assert tx % 16 == 0 and tx * ty * tz <= 32768 and ty * tz == 64
             assert (tz == 1) == (dim == 2)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark has a one-GPU path only: --gpus 2 stops with a message."""
+    import sys
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
