@@ -164,6 +164,22 @@ def test_full_size_first_sweeps(dim, L, T):
         _step_compare(lat, dim, L, seed, thr, spins, 2)
 
 
+@pytest.mark.parametrize("dim,L,T", [(2, 100, TC), (2, 36, 2.6), (3, 20, workloads.TC_3D),
+                                     (2, 64, TC), (2, 48, 2.1), (3, 24, 5.0)])
+def test_sweeps_without_labels_or_series(dim, L, T):
+    """Sweeps that keep no labels and record no series (the flip kernel's lean
+    path: groups of 4 sites when L is a multiple of 4 only, of 8 when of 8),
+    ragged tiles included: spins after each of three sweeps."""
+    seed = 9
+    with swgpu.Lattice(swgpu.make_params(dim, L, T=T, seed=seed)) as lat:
+        thr = lat.state()[2]
+        spins = oracle.init_spins(dim, L, seed)
+        for k in range(3):
+            lat.sweep(1)
+            spins, _ = oracle.sweep(dim, L, seed, k, thr, spins)
+            assert np.array_equal(lat.spins(), spins), f"spins differ after sweep {k} (dim={dim} L={L})"
+
+
 @pytest.mark.parametrize("dim,L,T,shape", [(2, 8192, TC, 0), (3, 256, workloads.TC_3D, 0),
                                            (3, 256, workloads.TC_3D, 1)])
 def test_full_size_bench_configuration(dim, L, T, shape):
