@@ -124,6 +124,20 @@ def test_pcc_plain_trace_growth_keeps_device_p():
         _check(lat, 0, spec, _oracle(spec, 18))
 
 
+@pytest.mark.parametrize("dim,L", [(2, 30), (3, 10)])
+def test_pcc_rows_not_in_quads(dim, L):
+    """PCC on lattices whose rows are not whole quads of sites (the flip kernel's
+    per-site coverage marks), plain and batched."""
+    spec = dict(dim=dim, L=L, seed=31, p_bond=0.45 if dim == 2 else 0.3, pcc=True, dp0=0.02, halve_every=5)
+    ref = _oracle(spec, 12)
+    for mode in (swgpu.SW_MODE_PLAIN, swgpu.SW_MODE_BATCHED):
+        with swgpu.Lattice(_params(spec)) as lat:
+            lat.set_mode(mode)
+            lat.sweep(5)
+            lat.sweep(7)
+            _check(lat, 0, spec, ref)
+
+
 def test_pcc_resume_sets_p():
     spec = dict(dim=2, L=24, seed=8, p_bond=0.5, pcc=True, dp0=0.02, halve_every=6)
     ref = _oracle(spec, 10)
