@@ -123,6 +123,17 @@ int sw_init(const sw_params* params, int32_t n_replicas, int32_t device, void* h
 /* Choose how sw_sweep runs the replicas (SW_MODE_PLAIN or SW_MODE_BATCHED). */
 int sw_set_mode(sw_lattice* h, int32_t mode);
 
+/* Launch shape of batched sweeps: per_cu = 0 runs the per-tile phases with one
+ * workgroup per tile of every active replica; per_cu in [1, 64] runs them with
+ * per_cu workgroups per compute unit, each taking a contiguous chunk of the
+ * (replica, tile) list.  Results never depend on it (every union hooks to the
+ * smaller root, so the schedule cannot change a label); the autotuner sets it
+ * too.  SW_EINVAL outside [0, 64]. */
+int sw_set_batch_grid(sw_lattice* h, int32_t per_cu);
+
+/* Current launch shape of batched sweeps (see sw_set_batch_grid). */
+int sw_get_batch_grid(sw_lattice* h, int32_t* per_cu);
+
 /*
  * Advance every replica by n_sweeps sweeps (Sec. I steps 1-3, plus the PCC
  * feedback of Sec. III for SW_PCC replicas).  Asynchronous on the stream.
@@ -136,10 +147,15 @@ int sw_sweep_replica(sw_lattice* h, int32_t replica, int32_t n_sweeps);
  * current configuration of a replica.  Synchronises. */
 int sw_measure(sw_lattice* h, int32_t replica, int64_t* e_int, int64_t* m);
 
-/* Copy the recorded (E_int, M) series (2 int64 per sweep, sweep 0 first) of a
- * SW_RECORD_SERIES replica into host_buf (cap int64 entries).  *count receives
- * the number of sweeps copied.  Synchronises. */
-int sw_get_series(sw_lattice* h, int32_t replica, int64_t* host_buf, int64_t cap, int64_t* count);
+/* Copy the recorded (E_int, M) series of a SW_RECORD_SERIES replica into
+ * host_buf (cap int64 entries, 2 per sweep): row j holds E_int and M of the
+ * configuration after sweep first + j, where first is the resume point of the
+ * last sw_set_spins (0 for a handle never rewound).  *count receives the
+ * number of rows copied, *first_sweep (may be NULL) the value of first.  Only
+ * measured rows are copied, never more than the device buffer holds.
+ * Synchronises. */
+int sw_get_series(sw_lattice* h, int32_t replica, int64_t* host_buf, int64_t cap, int64_t* count,
+                  int64_t* first_sweep);
 
 /* Copy the N spins of a replica to host memory (cap >= N).  Synchronises. */
 int sw_get_spins(sw_lattice* h, int32_t replica, int8_t* host_buf, int64_t cap);
@@ -152,14 +168,20 @@ int sw_get_labels(sw_lattice* h, int32_t replica, int32_t* host_buf, int64_t cap
  * replica.  Synchronises. */
 int sw_get_state(sw_lattice* h, int32_t replica, uint32_t* sweep, double* p, uint64_t* thr);
 
-/* Copy the per-sweep percolation flags and p values of a SW_PCC replica
- * (count = min(cap, sweeps done)).  Synchronises. */
+/* Copy the per-sweep percolation flags (extension rule, Sec. III) and the p
+ * values after each feedback step of a SW_PCC replica: entry j belongs to
+ * sweep first + j (first as in sw_get_series); count = min(cap, sweeps done
+ * since first).  perc or p may be NULL.  Synchronises. */
 int sw_get_pcc_trace(sw_lattice* h, int32_t replica, int32_t* perc, double* p, int64_t cap,
-                     int64_t* count);
+                     int64_t* count, int64_t* first_sweep);
 
 /* Replace a replica's spins (N int8 of +1/-1, host memory) and set its sweep
- * index to `sweep` (checkpoint / resume).  For SW_PCC replicas p (in [0,1])
- * becomes the current bond probability; otherwise p is ignored.  Synchronises. */
+ * index to `sweep` (checkpoint / resume), forward or back.  For SW_PCC
+ * replicas p (in [0,1]) becomes the current bond probability; otherwise p is
+ * ignored.  The series and PCC trace restart at `sweep` (their rows before it
+ * are dropped), and every per-sweep mark left by the abandoned trajectory is
+ * cleared, so the continuation equals a fresh run from this state.
+ * Synchronises. */
 int sw_set_spins(sw_lattice* h, int32_t replica, const int8_t* host_buf, int64_t n, uint32_t sweep,
                  double p);
 
@@ -214,7 +236,10 @@ enum { SW_JOB_QUEUED = 0, SW_JOB_RUNNING = 1, SW_JOB_DONE = 2, SW_JOB_REJECTED =
 
 /*
  * Create a server that keeps at most max_slots lattices resident and whose
- * resident device footprint never exceeds hbm_budget_bytes.  Each tick
+ * resident device footprint never exceeds hbm_budget_bytes (clamped to the
+ * device memory free at creation).  A job whose allocation fails on
+ * admission is rejected (SW_JOB_REJECTED); any other failure during admission
+ * leaves it queued and is returned by sw_server_step.  Each tick
  * (sw_server_step) runs up to `sweeps_per_tick` sweeps of every resident job
  * in one batched launch, then retires finished jobs and admits queued ones.
  */

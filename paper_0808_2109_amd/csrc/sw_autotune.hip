@@ -95,10 +95,12 @@ static int copy_state(sw_lattice* s, int r, const sw_lattice* h, int src)
     return push_desc(s, r);
 }
 
-// milliseconds per sweep of `sweeps` sweeps on handle s (after one untimed sweep)
+// milliseconds per sweep of `sweeps` sweeps on handle s, after an untimed call
+// of the same size (which, in batched mode, builds the graph the timed call
+// replays, so that graph capture stays outside the timed region)
 static int time_sweeps(sw_lattice* s, int sweeps, double* ms_out)
 {
-    int rc = sw_sweep(s, 1);
+    int rc = sw_sweep(s, sweeps);
     if (!rc) rc = handle_sync(s);
     if (rc) return rc;
     hipEvent_t a = nullptr, b = nullptr;
@@ -177,7 +179,7 @@ static int tune_batch(sw_lattice* h, int32_t sweeps, const char* cache_path)
             for (size_t r = 0; r < ps.size() && !rc; ++r) rc = sw_set_tile_shape(s, (int32_t)r, v);
             for (size_t r = 0; r < ps.size() && !rc; ++r) rc = copy_state(s, (int)r, h, (int)r);
             if (!rc) s->mode = SW_MODE_BATCHED;
-            for (int per_cu : {4, 8, 16}) {
+            for (int per_cu : {0, 4, 8, 16}) {
                 if (rc) break;
                 s->batch_per_cu = per_cu;
                 double ms = 0;
@@ -199,7 +201,7 @@ static int tune_batch(sw_lattice* h, int32_t sweeps, const char* cache_path)
         int rc = sw_set_tile_shape(h, (int32_t)r, best_v);
         if (rc) return rc;
     }
-    if (best_grid > 0) h->batch_per_cu = best_grid;
+    if (best_grid >= 0) h->batch_per_cu = best_grid;
     return SW_OK;
 }
 

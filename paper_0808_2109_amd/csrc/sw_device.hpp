@@ -61,10 +61,11 @@ struct SwRep {
     uint32_t sweep;             // sweeps done
     uint32_t limit;             // batched mode: never run past this sweep
     uint32_t measured;          // series entries complete (E,M after sweep k, k < measured)
+    uint32_t first;             // first sweep of the records: series row j and PCC trace entry j
+                                // belong to sweep first + j (the resume point of the last set_spins)
     uint32_t series_cap;        // entries the series buffer holds
     uint32_t trace_cap;         // entries the PCC trace buffers hold
     int32_t active;             // batched mode: replica takes part
-    int32_t pad0;
     int8_t* spins;              // N
     uint16_t* lab16;            // N tile-local labels (tile-local index of the cluster's tile root)
     int32_t* par;               // N global union-find parents (border roots only)

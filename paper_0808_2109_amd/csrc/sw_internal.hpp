@@ -25,12 +25,14 @@ int launch_cand(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream);
 int launch_perc(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream);
 int launch_measure(const SwRep& h, SwRep* d, int64_t* dst, hipStream_t stream);
 int launch_init(const SwRep& h, SwRep* d, hipStream_t stream);
-int launch_set_state(SwRep* d, uint32_t sweep, uint32_t measured, double p, uint64_t thr, int set_p,
+int launch_set_state(SwRep* d, uint32_t sweep, uint32_t measured, uint32_t first, double p, uint64_t thr, int set_p,
                      hipStream_t stream);
 // enqueue n sweeps of every active replica as batched phase launches (used
 // under stream capture to build the batch graph)
+// (grid: workgroups of the list-chunking kernels; item_grid: workgroups of the
+// per-tile phase kernels, nitems for one workgroup per work item)
 int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, int nitems, int n_sweeps, int any_pcc,
-                 int any_series, int any_3d, int grid, hipStream_t stream);
+                 int any_series, int any_3d, int grid, int item_grid, hipStream_t stream);
 
 int shape_count(int dim);
 int shape_extents(int dim, int id, int* tx, int* ty, int* tz);

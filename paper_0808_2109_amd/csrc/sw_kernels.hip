@@ -180,9 +180,9 @@ __device__ void pcc_update(SwRep* Rd, uint32_t s)
                        __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store((unsigned long long*)&Rd->thr, (unsigned long long)thr, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
-    if (s < Rd->trace_cap) {
-        Rd->perc_trace[s] = perc;
-        Rd->p_trace[s] = q;
+    if (s >= Rd->first && s - Rd->first < Rd->trace_cap) {
+        Rd->perc_trace[s - Rd->first] = perc;
+        Rd->p_trace[s - Rd->first] = q;
     }
 }
 
@@ -253,11 +253,13 @@ __global__ __launch_bounds__(kBlock) void kinit_kernel(const SwRep* Rd)
     }
 }
 
-__global__ void kset_state_kernel(SwRep* Rd, uint32_t sweep, uint32_t measured, double p, uint64_t thr, int set_p)
+__global__ void kset_state_kernel(SwRep* Rd, uint32_t sweep, uint32_t measured, uint32_t first, double p,
+                                  uint64_t thr, int set_p)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         Rd->sweep = sweep;
         Rd->measured = measured;
+        Rd->first = first;
         if (set_p) {
             Rd->p = p;
             Rd->thr = thr;
@@ -293,38 +295,47 @@ __device__ __forceinline__ void flush_em(int64_t e, int64_t m, int64_t* dst, int
 // K1 over the work list: one workgroup per item (grid = nitems, as many
 // threads as the larger of the two tiles needs), with E, M of the incoming
 // configuration added to the replica's series entry
+// The per-item kernels below take either one workgroup per work item (grid =
+// nitems) or a smaller grid whose workgroups each run a contiguous,
+// XCD-aware chunk of the list; the results are the same for any grid.
 template <class C2, class C3>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(k1_waves<C2>()))) void kb1_kernel(
     SwRep* reps, const EngineItem* items, int nitems, int it, int n_sweeps)
 {
     __shared__ __align__(16) char smem[cmax2(sizeof(K1Smem<C2>), sizeof(K1Smem<C3>))];
-    const int i = blockIdx.x;
-    if (i >= nitems) return;
-    const SwRep& R = reps[items[i].rep];
-    uint32_t s;
-    if (!rep_runs(R, it, n_sweeps, s)) return;
-    int64_t* dst = nullptr;
-    if ((R.flags & FLAG_SERIES) && s >= 1 && (it > 0 || R.measured < R.sweep)) dst = R.series + 2 * (size_t)(s - 1);
-    int64_t e = 0, m = 0;
-    if (R.dim == 2)
-        k1_tile<C2>(R, items[i].tile, s, R.thr, *reinterpret_cast<K1Smem<C2>*>(smem), dst != nullptr, e, m);
-    else
-        k1_tile<C3>(R, items[i].tile, s, R.thr, *reinterpret_cast<K1Smem<C3>*>(smem), dst != nullptr, e, m);
-    if (dst) wave_flush_em(e, m, dst);
+    int i0, i1;
+    chunk_of(nitems, i0, i1);
+    for (int i = i0; i < i1; ++i) {
+        const SwRep& R = reps[items[i].rep];
+        uint32_t s;
+        if (!rep_runs(R, it, n_sweeps, s)) continue;
+        int64_t* dst = nullptr;
+        if ((R.flags & FLAG_SERIES) && s >= 1 && (it > 0 || R.measured < R.sweep))
+            dst = R.series + 2 * (size_t)(s - 1 - R.first);
+        int64_t e = 0, m = 0;
+        if (R.dim == 2)
+            k1_tile<C2>(R, items[i].tile, s, R.thr, *reinterpret_cast<K1Smem<C2>*>(smem), dst != nullptr, e, m);
+        else
+            k1_tile<C3>(R, items[i].tile, s, R.thr, *reinterpret_cast<K1Smem<C3>*>(smem), dst != nullptr, e, m);
+        if (dst) wave_flush_em(e, m, dst);
+    }
 }
 
-// K2: one workgroup per work item (launched with grid = nitems)
+// K2 over the work list
 template <class C2, class C3>
 __global__ __launch_bounds__(kBlock) void kb2_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
                                                      int n_sweeps)
 {
     __shared__ __align__(16) char smem[cmax2(sizeof(K2Smem<C2>), sizeof(K2Smem<C3>))];
-    const int i = xcd_item(nitems);
-    const SwRep& R = reps[items[i].rep];
-    uint32_t s;
-    if (!rep_runs(R, it, n_sweeps, s)) return;
-    if (R.dim == 2) k2_tile<C2>(R, items[i].tile, *reinterpret_cast<K2Smem<C2>*>(smem));
-    else k2_tile<C3>(R, items[i].tile, *reinterpret_cast<K2Smem<C3>*>(smem));
+    int i0, i1;
+    chunk_of(nitems, i0, i1);
+    for (int i = i0; i < i1; ++i) {
+        const SwRep& R = reps[items[i].rep];
+        uint32_t s;
+        if (!rep_runs(R, it, n_sweeps, s)) continue;
+        if (R.dim == 2) k2_tile<C2>(R, items[i].tile, *reinterpret_cast<K2Smem<C2>*>(smem));
+        else k2_tile<C3>(R, items[i].tile, *reinterpret_cast<K2Smem<C3>*>(smem));
+    }
 }
 
 template <class C2, class C3>
@@ -347,12 +358,16 @@ __global__ __launch_bounds__(64) void kb3a_kernel(SwRep* reps, const EngineItem*
                                                   int n_sweeps)
 {
     __shared__ __align__(16) char smem[cmax2(sizeof(K3aSmem<C2>), sizeof(K3aSmem<C3>))];
-    const int i = xcd_item(nitems);
-    const SwRep& R = reps[items[i].rep];
-    uint32_t s;
-    if (!rep_runs(R, it, n_sweeps, s)) return;
-    if (R.dim == 2) k3a_tile<C2>(R, items[i].tile, s, *reinterpret_cast<K3aSmem<C2>*>(smem));
-    else k3a_tile<C3>(R, items[i].tile, s, *reinterpret_cast<K3aSmem<C3>*>(smem));
+    int i0, i1;
+    chunk_of(nitems, i0, i1);
+    for (int i = i0; i < i1; ++i) {
+        const SwRep& R = reps[items[i].rep];
+        uint32_t s;
+        if (!rep_runs(R, it, n_sweeps, s)) continue;
+        wave_lds_sync();   // the previous item's reads of the tables are done
+        if (R.dim == 2) k3a_tile<C2>(R, items[i].tile, s, *reinterpret_cast<K3aSmem<C2>*>(smem));
+        else k3a_tile<C3>(R, items[i].tile, s, *reinterpret_cast<K3aSmem<C3>*>(smem));
+    }
 }
 
 template <class C2, class C3>
@@ -360,12 +375,15 @@ __global__ __launch_bounds__(kK3Block) void kb3_kernel(SwRep* reps, const Engine
                                                      int n_sweeps)
 {
     __shared__ __align__(16) char smem[cmax2(sizeof(K3Smem<C2>), sizeof(K3Smem<C3>))];
-    const int i = xcd_item(nitems);
-    const SwRep& R = reps[items[i].rep];
-    uint32_t s;
-    if (!rep_runs(R, it, n_sweeps, s)) return;
-    if (R.dim == 2) k3_tile<C2>(R, items[i].tile, s, *reinterpret_cast<K3Smem<C2>*>(smem));
-    else k3_tile<C3>(R, items[i].tile, s, *reinterpret_cast<K3Smem<C3>*>(smem));
+    int i0, i1;
+    chunk_of(nitems, i0, i1);
+    for (int i = i0; i < i1; ++i) {
+        const SwRep& R = reps[items[i].rep];
+        uint32_t s;
+        if (!rep_runs(R, it, n_sweeps, s)) continue;
+        if (R.dim == 2) k3_tile<C2>(R, items[i].tile, s, *reinterpret_cast<K3Smem<C2>*>(smem));
+        else k3_tile<C3>(R, items[i].tile, s, *reinterpret_cast<K3Smem<C3>*>(smem));
+    }
 }
 
 // PCC coverage test: tile t of a replica checks its share of the candidate slots
@@ -422,7 +440,7 @@ __global__ __launch_bounds__(kBlock) void kbm_kernel(SwRep* reps, const EngineIt
                 const SwRep& R = reps[rep];
                 const uint64_t target = min((uint64_t)R.sweep + (uint64_t)n_sweeps, (uint64_t)R.limit);
                 if (R.active && (R.flags & FLAG_SERIES) && target >= 1 && R.measured < target)
-                    dst = R.series + 2 * (size_t)(target - 1);
+                    dst = R.series + 2 * (size_t)(target - 1 - R.first);
             }
         }
         if (i == i1) break;
@@ -570,28 +588,29 @@ int launch_init(const SwRep& h, SwRep* d, hipStream_t stream)
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-int launch_set_state(SwRep* d, uint32_t sweep, uint32_t measured, double p, uint64_t thr, int set_p,
+int launch_set_state(SwRep* d, uint32_t sweep, uint32_t measured, uint32_t first, double p, uint64_t thr, int set_p,
                      hipStream_t stream)
 {
-    hipLaunchKernelGGL(kset_state_kernel, dim3(1), dim3(64), 0, stream, d, sweep, measured, p, thr, set_p);
+    hipLaunchKernelGGL(kset_state_kernel, dim3(1), dim3(64), 0, stream, d, sweep, measured, first, p, thr, set_p);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
 int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, int nitems, int n_sweeps, int any_pcc,
-                 int any_series, int any_3d, int grid, hipStream_t stream)
+                 int any_series, int any_3d, int grid, int item_grid, hipStream_t stream)
 {
     const int rgrid = (nreps + kBlock - 1) / kBlock;
+    const int ig = item_grid;
     switch (variant) {
 #define SW_BATCH(i, C2, C3)                                                                                          \
     case i:                                                                                                          \
         for (int it = 0; it < n_sweeps; ++it) {                                                                      \
-            hipLaunchKernelGGL((kb1_kernel<C2, C3>), dim3(nitems), dim3(max(K1Cfg<C2>::NT, K1Cfg<C3>::NT)), 0, stream, reps, items, nitems, it, n_sweeps); \
-            hipLaunchKernelGGL((kb2_kernel<C2, C3>), dim3(nitems), dim3(any_3d ? kBlock : K2Cfg<C2>::NT), 0, stream,     \
+            hipLaunchKernelGGL((kb1_kernel<C2, C3>), dim3(ig), dim3(max(K1Cfg<C2>::NT, K1Cfg<C3>::NT)), 0, stream, reps, items, nitems, it, n_sweeps); \
+            hipLaunchKernelGGL((kb2_kernel<C2, C3>), dim3(ig), dim3(any_3d ? kBlock : K2Cfg<C2>::NT), 0, stream,     \
                                reps, items, nitems, it, n_sweeps);                                                   \
-            hipLaunchKernelGGL((kb3a_kernel<C2, C3>), dim3(nitems), dim3(64), 0, stream, reps, items, nitems, it, n_sweeps); \
+            hipLaunchKernelGGL((kb3a_kernel<C2, C3>), dim3(ig), dim3(64), 0, stream, reps, items, nitems, it, n_sweeps); \
             if (any_pcc)                                                                                             \
                 hipLaunchKernelGGL((kbc_kernel<C2, C3>), dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
-            hipLaunchKernelGGL((kb3_kernel<C2, C3>), dim3(nitems), dim3(kK3Block), 0, stream, reps, items, nitems, it, n_sweeps); \
+            hipLaunchKernelGGL((kb3_kernel<C2, C3>), dim3(ig), dim3(kK3Block), 0, stream, reps, items, nitems, it, n_sweeps); \
             if (any_pcc) {                                                                                           \
                 hipLaunchKernelGGL(kbp_kernel, dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
                 hipLaunchKernelGGL(kbu_kernel, dim3(rgrid), dim3(kBlock), 0, stream, reps, nreps, it, n_sweeps);     \

@@ -381,11 +381,13 @@ static int grow(void** buf, uint32_t old_cap, uint32_t new_cap, size_t elem, hip
     return SW_OK;
 }
 
-// make the series / PCC traces hold `need` sweeps
-int ensure_capacity(sw_lattice* h, int r, uint64_t need)
+// make the series / PCC traces hold the records up to sweep `upto` (exclusive);
+// records start at the replica's resume point m.first
+int ensure_capacity(sw_lattice* h, int r, uint64_t upto)
 {
     SwRep& m = h->reps[r].h;
-    if (need > 0xFFFFFFF0ull) return fail(SW_EINVAL, "sweep index overflow");
+    if (upto > 0xFFFFFFF0ull) return fail(SW_EINVAL, "sweep index overflow");
+    const uint64_t need = upto > m.first ? upto - m.first : 0;
     bool changed = false;
     if ((m.flags & FLAG_SERIES) && need > m.series_cap) {
         int rc = refresh_mirror(h);
@@ -488,7 +490,7 @@ int plain_sweep(sw_lattice* h, int r, int32_t n)
         const uint32_t s = m.sweep + (uint32_t)k;
         int64_t* em = nullptr;
         if (series && s >= 1 && m.measured < s) {
-            em = m.series + 2 * (size_t)(s - 1);
+            em = m.series + 2 * (size_t)(s - 1 - m.first);   // measured >= first, so s - 1 >= first
             m.measured = s;
         }
         TIMED(h, 0, launch_k1(m, d, s, em, h->stream, h->per_cu[0]));
@@ -501,7 +503,7 @@ int plain_sweep(sw_lattice* h, int r, int32_t n)
     if (pcc && n > 0) h->mirror_stale = true;   // p and thr now change on the device
     m.sweep += (uint32_t)n;
     if (series && n > 0 && m.measured < m.sweep) {
-        TIMED(h, 4, launch_measure(m, d, m.series + 2 * (size_t)(m.sweep - 1), h->stream));
+        TIMED(h, 4, launch_measure(m, d, m.series + 2 * (size_t)(m.sweep - 1 - m.first), h->stream));
         m.measured = m.sweep;
     }
     if (n > 0) {
@@ -571,7 +573,7 @@ int batched_sweep(sw_lattice* h, int32_t n)
     for (auto& rep : h->reps) {
         if (!rep.dev_count_stale) continue;
         const SwRep& m = rep.h;
-        if (launch_set_state(&h->d_reps[&rep - h->reps.data()], m.sweep, m.measured, 0.0, 0, 0, h->stream))
+        if (launch_set_state(&h->d_reps[&rep - h->reps.data()], m.sweep, m.measured, m.first, 0.0, 0, 0, h->stream))
             return fail(SW_EHIP, "state update launch failed");
         rep.dev_count_stale = false;
     }
@@ -593,16 +595,24 @@ int batched_sweep(sw_lattice* h, int32_t n)
     int variant = 0;
     rc = engine_variant(h, &variant);
     if (rc) return rc;
-    int grid = std::min(device_cu_count() * h->batch_per_cu, h->nitems);
-    if (grid >= 8) grid -= grid % 8;
-    if (grid < 1) grid = 1;
-    if (h->graph_n != n || h->graph_grid != grid || h->graph_flags != (int)(any_3d * 4 + any_pcc * 2 + any_series) ||
-        h->graph_variant != variant) {
+    // list-chunking kernels: per_cu workgroups per CU (8 when the phase
+    // kernels take one workgroup per tile); phase kernels: one workgroup per
+    // tile, or per_cu per CU each running a chunk of the list
+    auto clamp_grid = [&](int g) {
+        g = std::min(g, h->nitems);
+        if (g >= 8) g -= g % 8;
+        return g < 1 ? 1 : g;
+    };
+    const int per_cu = h->batch_per_cu;
+    const int grid = clamp_grid(device_cu_count() * (per_cu > 0 ? per_cu : 8));
+    const int item_grid = per_cu > 0 ? clamp_grid(device_cu_count() * per_cu) : h->nitems;
+    if (h->graph_n != n || h->graph_grid != grid || h->graph_item_grid != item_grid ||
+        h->graph_flags != (int)(any_3d * 4 + any_pcc * 2 + any_series) || h->graph_variant != variant) {
         drop_graph(h);
         hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
         int lrc = launch_batch(variant, h->d_reps, (int)h->reps.size(), h->items, h->nitems, n, any_pcc, any_series,
-                               any_3d, grid, h->stream);
+                               any_3d, grid, item_grid, h->stream);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(h->stream, &g);
         if (lrc || e != hipSuccess || !g) {
@@ -617,6 +627,7 @@ int batched_sweep(sw_lattice* h, int32_t n)
         }
         h->graph_n = n;
         h->graph_grid = grid;
+        h->graph_item_grid = item_grid;
         h->graph_flags = (int)(any_3d * 4 + any_pcc * 2 + any_series);
         h->graph_variant = variant;
     }
@@ -726,6 +737,21 @@ int sw_set_mode(sw_lattice* h, int32_t mode)
     return SW_OK;
 }
 
+int sw_set_batch_grid(sw_lattice* h, int32_t per_cu)
+{
+    if (!h) return fail(SW_EINVAL, "null handle");
+    if (per_cu < 0 || per_cu > 64) return fail(SW_EINVAL, "workgroups per CU must be in [0, 64] (got %d)", per_cu);
+    h->batch_per_cu = per_cu;
+    return SW_OK;
+}
+
+int sw_get_batch_grid(sw_lattice* h, int32_t* per_cu)
+{
+    if (!h || !per_cu) return fail(SW_EINVAL, "null argument");
+    *per_cu = h->batch_per_cu;
+    return SW_OK;
+}
+
 int sw_sweep(sw_lattice* h, int32_t n_sweeps)
 {
     if (!h) return fail(SW_EINVAL, "null handle");
@@ -770,7 +796,8 @@ int sw_measure(sw_lattice* h, int32_t replica, int64_t* e_int, int64_t* m)
     return SW_OK;
 }
 
-int sw_get_series(sw_lattice* h, int32_t replica, int64_t* host_buf, int64_t cap, int64_t* count)
+int sw_get_series(sw_lattice* h, int32_t replica, int64_t* host_buf, int64_t cap, int64_t* count,
+                  int64_t* first_sweep)
 {
     int rc = check_rep(h, replica);
     if (rc) return rc;
@@ -780,12 +807,15 @@ int sw_get_series(sw_lattice* h, int32_t replica, int64_t* host_buf, int64_t cap
     rc = set_device(h);
     if (!rc) rc = sync_mirror(h);
     if (rc) return rc;
-    const int64_t nrec = std::min<int64_t>(m.measured, cap / 2);
+    // rows of the sweeps [first, measured): never more than the buffer holds
+    const int64_t have = m.measured > m.first ? (int64_t)(m.measured - m.first) : 0;
+    const int64_t nrec = std::min<int64_t>(std::min<int64_t>(have, (int64_t)m.series_cap), cap / 2);
     if (nrec > 0) {
         hipError_t e = hipMemcpy(host_buf, m.series, (size_t)nrec * 16, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "reading the series");
     }
     *count = nrec;
+    if (first_sweep) *first_sweep = m.first;
     return SW_OK;
 }
 
@@ -833,7 +863,8 @@ int sw_get_state(sw_lattice* h, int32_t replica, uint32_t* sweep, double* p, uin
     return SW_OK;
 }
 
-int sw_get_pcc_trace(sw_lattice* h, int32_t replica, int32_t* perc, double* p, int64_t cap, int64_t* count)
+int sw_get_pcc_trace(sw_lattice* h, int32_t replica, int32_t* perc, double* p, int64_t cap, int64_t* count,
+                     int64_t* first_sweep)
 {
     int rc = check_rep(h, replica);
     if (rc) return rc;
@@ -843,7 +874,8 @@ int sw_get_pcc_trace(sw_lattice* h, int32_t replica, int32_t* perc, double* p, i
     rc = set_device(h);
     if (!rc) rc = sync_mirror(h);
     if (rc) return rc;
-    const int64_t n = std::min<int64_t>(std::min<int64_t>(m.sweep, m.trace_cap), cap);
+    const int64_t have = m.sweep > m.first ? (int64_t)(m.sweep - m.first) : 0;
+    const int64_t n = std::min<int64_t>(std::min<int64_t>(have, (int64_t)m.trace_cap), cap);
     if (n > 0 && perc) {
         hipError_t e = hipMemcpy(perc, m.perc_trace, (size_t)n * 4, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "reading the percolation trace");
@@ -853,6 +885,7 @@ int sw_get_pcc_trace(sw_lattice* h, int32_t replica, int32_t* perc, double* p, i
         if (e != hipSuccess) return hip_fail(e, "reading the p trace");
     }
     *count = n;
+    if (first_sweep) *first_sweep = m.first;
     return SW_OK;
 }
 
@@ -872,14 +905,29 @@ int sw_set_spins(sw_lattice* h, int32_t replica, const int8_t* host_buf, int64_t
     if (rc) return rc;
     hipError_t e = hipMemcpy(m.spins, host_buf, (size_t)n, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "writing spins");
+    // The records restart at the resume point.  Series rows are accumulated
+    // with atomic adds, so the reused rows are cleared; PCC candidate marks
+    // carry the tag of the sweep that wrote them, and a tag left by a later
+    // sweep of the abandoned trajectory would outrank this one's, so they are
+    // cleared too (with the coverage bitmaps and the flag, which are zero
+    // between sweeps anyway).
     m.sweep = sweep;
     m.measured = sweep;
+    m.first = sweep;
+    if ((m.flags & FLAG_SERIES) && hipMemsetAsync(m.series, 0, (size_t)m.series_cap * 16, h->stream) != hipSuccess)
+        return fail(SW_EHIP, "clearing the series failed");
     if (pcc) {
         m.p = p;
         m.thr = threshold_from_p(p);
+        const size_t L = (size_t)m.L;
+        const size_t ns = (m.dim == 3) ? L * L : L;
+        if (hipMemsetAsync(m.cand, 0, (size_t)m.dim * m.N * 8, h->stream) != hipSuccess ||
+            hipMemsetAsync(m.bmp, 0, (size_t)m.dim * ns * ((L + 31) / 32) * 4, h->stream) != hipSuccess ||
+            hipMemsetAsync(m.pflag, 0, 16, h->stream) != hipSuccess)
+            return fail(SW_EHIP, "clearing the percolation buffers failed");
     }
     h->reps[replica].labels_valid = false;
-    if (launch_set_state(&h->d_reps[replica], m.sweep, m.measured, m.p, m.thr, pcc ? 1 : 0, h->stream))
+    if (launch_set_state(&h->d_reps[replica], m.sweep, m.measured, m.first, m.p, m.thr, pcc ? 1 : 0, h->stream))
         return fail(SW_EHIP, "state update launch failed");
     h->reps[replica].dev_count_stale = false;
     return handle_sync(h);

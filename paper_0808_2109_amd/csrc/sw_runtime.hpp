@@ -62,11 +62,12 @@ struct sw_lattice {
     size_t items_cap = 0;
     int nitems = 0;
     bool items_dirty = true;
-    int batch_per_cu = 8;               // workgroups per CU of the batched launches
+    int batch_per_cu = 0;               // workgroups per CU of the batched phase launches (0: one per tile)
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int graph_n = -1;
     int graph_grid = -1;
+    int graph_item_grid = -1;
     int graph_flags = -1;
     int graph_variant = -1;
 };

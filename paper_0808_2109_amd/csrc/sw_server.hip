@@ -97,17 +97,33 @@ static int admit(sw_server* s)
                 break;
             }
         if (slot < 0 || s->in_use + j.bytes > s->budget) break;   // arrival order: no overtaking
-        s->queue.pop_front();
         ReplicaH& r = s->lat->reps[slot];
         int rc = replica_alloc(r, &j.prm, default_shape(j.prm.dim), s->lat->stream);
-        if (rc) return rc;
+        if (rc) {
+            // the slot stays free (replica_alloc released what it took); the
+            // device descriptor of the slot was never touched
+            std::memset(&r.h, 0, sizeof(r.h));
+            r.h.active = 0;
+            if (rc != SW_ENOMEM) return rc;   // the job stays queued
+            // the device could not hold the job even within the budget: it is
+            // rejected rather than retried forever
+            s->queue.pop_front();
+            j.state = SW_JOB_REJECTED;
+            j.t_done = s->now();
+            s->n_rejected += 1;
+            continue;
+        }
         r.h.limit = (uint32_t)j.n_sweeps;
         r.h.active = 1;
         r.h.err = s->lat->err;
         r.labels_valid = false;
         rc = push_desc(s->lat, slot);
-        if (rc) return rc;
-        if (launch_init(r.h, &s->lat->d_reps[slot], s->lat->stream)) return fail(SW_EHIP, "init launch failed");
+        if (!rc && launch_init(r.h, &s->lat->d_reps[slot], s->lat->stream)) rc = fail(SW_EHIP, "init launch failed");
+        if (rc) {
+            const int frc = free_slot(s, slot);   // the job stays queued
+            return frc ? frc : rc;
+        }
+        s->queue.pop_front();
         s->slot_job[slot] = j.id;
         s->lat->items_dirty = true;
         s->in_use += j.bytes;
@@ -181,6 +197,10 @@ int sw_server_create(uint64_t hbm_budget_bytes, int32_t max_slots, int32_t sweep
     }
     s->lat = lat;
     s->lat->mode = SW_MODE_BATCHED;
+    // the budget never exceeds the device memory free at creation
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && (uint64_t)free_b < hbm_budget_bytes)
+        hbm_budget_bytes = (uint64_t)free_b;
     s->budget = hbm_budget_bytes;
     s->max_slots = max_slots;
     s->tick = sweeps_per_tick;

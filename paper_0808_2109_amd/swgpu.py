@@ -74,14 +74,16 @@ def lib():
         "sw_last_error": (c.c_char_p, []),
         "sw_init": (c.c_int, [P(sw_params), c.c_int32, c.c_int32, vp, P(vp)]),
         "sw_set_mode": (c.c_int, [vp, c.c_int32]),
+        "sw_set_batch_grid": (c.c_int, [vp, c.c_int32]),
+        "sw_get_batch_grid": (c.c_int, [vp, P(c.c_int32)]),
         "sw_sweep": (c.c_int, [vp, c.c_int32]),
         "sw_sweep_replica": (c.c_int, [vp, c.c_int32, c.c_int32]),
         "sw_measure": (c.c_int, [vp, c.c_int32, P(c.c_int64), P(c.c_int64)]),
-        "sw_get_series": (c.c_int, [vp, c.c_int32, vp, c.c_int64, P(c.c_int64)]),
+        "sw_get_series": (c.c_int, [vp, c.c_int32, vp, c.c_int64, P(c.c_int64), P(c.c_int64)]),
         "sw_get_spins": (c.c_int, [vp, c.c_int32, vp, c.c_int64]),
         "sw_get_labels": (c.c_int, [vp, c.c_int32, vp, c.c_int64]),
         "sw_get_state": (c.c_int, [vp, c.c_int32, P(c.c_uint32), P(c.c_double), P(c.c_uint64)]),
-        "sw_get_pcc_trace": (c.c_int, [vp, c.c_int32, vp, vp, c.c_int64, P(c.c_int64)]),
+        "sw_get_pcc_trace": (c.c_int, [vp, c.c_int32, vp, vp, c.c_int64, P(c.c_int64), P(c.c_int64)]),
         "sw_set_spins": (c.c_int, [vp, c.c_int32, vp, c.c_int64, c.c_uint32, c.c_double]),
         "sw_bind_device_spins": (c.c_int, [vp, c.c_int32, vp]),
         "sw_set_timing": (c.c_int, [vp, c.c_int32]),
@@ -198,6 +200,15 @@ class Lattice:
     def set_mode(self, mode: int):
         _check(lib().sw_set_mode(self._h, mode))
 
+    def set_batch_grid(self, per_cu: int):
+        """Workgroups per CU of batched sweeps (0: one per tile)."""
+        _check(lib().sw_set_batch_grid(self._h, per_cu))
+
+    def batch_grid(self) -> int:
+        v = ctypes.c_int32()
+        _check(lib().sw_get_batch_grid(self._h, ctypes.byref(v)))
+        return int(v.value)
+
     def sweep(self, n: int = 1):
         _check(lib().sw_sweep(self._h, n))
 
@@ -211,13 +222,17 @@ class Lattice:
         _check(lib().sw_measure(self._h, r, ctypes.byref(e), ctypes.byref(m)))
         return int(e.value), int(m.value)
 
-    def series(self, r: int = 0) -> np.ndarray:
+    def series(self, r: int = 0, with_first: bool = False):
+        """(E_int, M) rows of the sweeps first, first + 1, ... (first = the last resume point)."""
         st = self.state(r)
         cap = 2 * max(st[0], 1)
         buf = np.zeros(cap, dtype=np.int64)
         cnt = ctypes.c_int64()
-        _check(lib().sw_get_series(self._h, r, buf.ctypes.data_as(ctypes.c_void_p), cap, ctypes.byref(cnt)))
-        return buf[: 2 * cnt.value].reshape(-1, 2)
+        first = ctypes.c_int64()
+        _check(lib().sw_get_series(self._h, r, buf.ctypes.data_as(ctypes.c_void_p), cap, ctypes.byref(cnt),
+                                   ctypes.byref(first)))
+        rows = buf[: 2 * cnt.value].reshape(-1, 2)
+        return (rows, int(first.value)) if with_first else rows
 
     def spins(self, r: int = 0) -> np.ndarray:
         n = self.nsites(r)
@@ -238,14 +253,17 @@ class Lattice:
         _check(lib().sw_get_state(self._h, r, ctypes.byref(s), ctypes.byref(p), ctypes.byref(t)))
         return int(s.value), float(p.value), int(t.value)
 
-    def pcc_trace(self, r: int = 0):
+    def pcc_trace(self, r: int = 0, with_first: bool = False):
+        """Percolation flags and p after each feedback step, from sweep `first` on."""
         n = self.state(r)[0]
         perc = np.zeros(max(n, 1), dtype=np.int32)
         pv = np.zeros(max(n, 1), dtype=np.float64)
         cnt = ctypes.c_int64()
+        first = ctypes.c_int64()
         _check(lib().sw_get_pcc_trace(self._h, r, perc.ctypes.data_as(ctypes.c_void_p),
-                                      pv.ctypes.data_as(ctypes.c_void_p), n, ctypes.byref(cnt)))
-        return perc[: cnt.value], pv[: cnt.value]
+                                      pv.ctypes.data_as(ctypes.c_void_p), n, ctypes.byref(cnt), ctypes.byref(first)))
+        out = (perc[: cnt.value], pv[: cnt.value])
+        return (*out, int(first.value)) if with_first else out
 
     # -- write
     def set_spins(self, r: int, spins: np.ndarray, sweep: int = 0, p: float = -1.0):

@@ -139,3 +139,58 @@ def test_streams_are_keyed_by_seed_sweep_and_index(orc):
     assert 128 - 40 < ups < 128 + 40
     init = [orc.init_spin(1, i) for i in range(4096)]
     assert abs(sum(init)) < 5 * 64
+
+
+# --------------------------------------------------------------------------- #
+# Known answers for the initial-spin and cluster-flip layouts, rebuilt here
+# from the Philox block alone (itself pinned above against ATen and rocRAND):
+# the spin of index k is bit k mod 32 of word (k >> 5) mod 4 of the block
+# k >> 7, counter (k >> 7, 0, sweep, tag), tag 0 for the start, 3 for flips.
+# A wrong word index, bit index, block counter, sweep slot or tag in either
+# oracle function changes some of these values.
+# --------------------------------------------------------------------------- #
+def _layout_bit(orc, seed, sweep, tag, k):
+    blk = orc.philox([k >> 7, 0, sweep, tag], [seed & 0xFFFFFFFF, seed >> 32])
+    return +1 if (int(blk[(k >> 5) & 3]) >> (k & 31)) & 1 else -1
+
+
+def _layout_indices():
+    rng = np.random.default_rng(41)
+    # three whole blocks (every bit of every word), block and word edges, and
+    # random indices up to the largest site index a lattice can have
+    idx = list(range(0, 384)) + [127, 128, 129, 255, 256, 4095, 4096, 2**20 - 1, 2**20, 2**31 - 2]
+    return idx + rng.integers(0, 2**31 - 1, size=500).tolist()
+
+
+@pytest.mark.parametrize("seed", [1, 0xDEADBEEF12345678])
+def test_initial_spin_layout_known_answers(orc, seed):
+    for k in _layout_indices():
+        assert orc.init_spin(seed, k) == _layout_bit(orc, seed, 0, 0, k), k
+
+
+@pytest.mark.parametrize("seed,sweep", [(1, 0), (5, 1), (0xDEADBEEF12345678, 977)])
+def test_flip_spin_layout_known_answers(orc, seed, sweep):
+    for r in _layout_indices():
+        assert orc.flip_spin(seed, sweep, r) == _layout_bit(orc, seed, sweep, 3, r), r
+
+
+def test_initial_block_carries_all_128_bits(orc):
+    """Sites 128..255 take the 128 bits of block 1 in order: word 0 bits 0..31,
+    then word 1, 2, 3."""
+    seed = 77
+    blk = orc.philox([1, 0, 0, 0], [seed, 0])
+    bits = [(int(blk[w]) >> b) & 1 for w in range(4) for b in range(32)]
+    got = [1 if orc.init_spin(seed, 128 + j) > 0 else 0 for j in range(128)]
+    assert got == bits
+
+
+def test_lattice_start_and_flip_follow_the_layout(orc):
+    """The lattice-level helpers use the same layout: the start of a 3D lattice
+    and the flip of a labelled lattice, site by site."""
+    dim, L, seed = 3, 9, 12345
+    sp = orc.init_spins(dim, L, seed)
+    assert [int(v) for v in sp] == [_layout_bit(orc, seed, 0, 0, k) for k in range(L ** dim)]
+    rng = np.random.default_rng(5)
+    labels = np.sort(rng.integers(0, L ** dim, size=L ** dim)).astype(np.int32)
+    fl = orc.flip(dim, L, seed, 6, labels)
+    assert [int(v) for v in fl] == [_layout_bit(orc, seed, 6, 3, int(r)) for r in labels]
