@@ -221,6 +221,34 @@ int sw_tile_shapes(int32_t dim, int32_t* count, int32_t* tx, int32_t* ty, int32_
  */
 int sw_autotune(sw_lattice* h, int32_t sweeps, const char* cache_path);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): n_sweeps
+ * sweeps of one lattice, as sw_sweep runs them on a handle, with no handle and
+ * no allocation.  Asynchronous on hip_stream (NULL: the null stream).
+ *   params      dim, L, J, T, p_bond, seed as for sw_init; SW_PCC is refused,
+ *               the other flags are ignored (the outputs below decide)
+ *   dev_spins   device array of N int8 +1/-1, x fastest: the configuration
+ *               before sweep sweep0 on entry, after sweep sweep0+n_sweeps-1
+ *               on return (caller-owned, read and written in place)
+ *   sweep0      index of the first sweep (keys the random stream)
+ *   dev_series  NULL, or a device array of 2*n_sweeps int64: row k receives
+ *               E_int and M after sweep sweep0+k (the call clears it first)
+ *   dev_labels  NULL, or a device array of N int32: the canonical labels of
+ *               the last sweep
+ *   dev_err     NULL, or a device int32 the caller has zeroed: nonzero after
+ *               the call completes if a device consistency check failed
+ * Every other buffer comes from a static device array of 20 MiB per device
+ * (held until the process ends), so lattices are limited to N <= 2^21 sites
+ * (1448^2, 128^3): larger ones, and a null spin array, give SW_EINVAL before
+ * anything is enqueued.  All calls on one device share that array: calls that
+ * overlap on one device (other streams, other threads) race and must be
+ * serialised by the caller.  The results equal those of sw_init + sw_set_spins
+ * (sweep0) + sw_sweep(n_sweeps) bit for bit.
+ */
+int sw_sweep_noalloc(const sw_params* params, int8_t* dev_spins, uint32_t sweep0, int32_t n_sweeps,
+                     int64_t* dev_series, int32_t* dev_labels, int32_t* dev_err, void* hip_stream);
+
 /* Release every resource the handle owns.  NULL is accepted. */
 int sw_free(sw_lattice* h);
 

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libswgpu.so")
-SOURCES = ["sw_kernels.hip", "sw_runtime.hip", "sw_autotune.hip", "sw_server.hip"]
+SOURCES = ["sw_kernels.hip", "sw_runtime.hip", "sw_autotune.hip", "sw_server.hip", "sw_noalloc.hip"]
 ARCH = os.environ.get("SW_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

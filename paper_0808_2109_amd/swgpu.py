@@ -93,6 +93,7 @@ def lib():
         "sw_tile_shapes": (c.c_int, [c.c_int32, P(c.c_int32), P(c.c_int32), P(c.c_int32), P(c.c_int32), c.c_int32]),
         "sw_autotune": (c.c_int, [vp, c.c_int32, c.c_char_p]),
         "sw_free": (c.c_int, [vp]),
+        "sw_sweep_noalloc": (c.c_int, [P(sw_params), vp, c.c_uint32, c.c_int32, vp, vp, vp, vp]),
         "sw_server_create": (c.c_int, [c.c_uint64, c.c_int32, c.c_int32, c.c_int32, vp, P(vp)]),
         "sw_server_submit": (c.c_int, [vp, P(sw_params), c.c_int32, P(c.c_uint64)]),
         "sw_server_footprint": (c.c_int, [P(sw_params), P(c.c_uint64)]),
@@ -299,6 +300,25 @@ class Lattice:
         n = (ctypes.c_int64 * k)()
         _check(lib().sw_get_timing(self._h, ms, n, k))
         return {PHASES[i]: (float(ms[i]), int(n[i])) for i in range(k)}
+
+
+def sweep_noalloc(params: sw_params, spins, n_sweeps: int, sweep0: int = 0, series=None, labels=None, err=None,
+                  stream="torch"):
+    """sw_sweep_noalloc on caller-owned torch device tensors (spins int8 of N;
+    optional series int64 of 2*n_sweeps, labels int32 of N, err int32 of 1)."""
+    def ptr(t, dtype, n):
+        if t is None:
+            return None
+        if str(t.dtype) != dtype or t.numel() != n or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError(f"need a contiguous {dtype} device tensor of {n} elements")
+        return ctypes.c_void_p(t.data_ptr())
+
+    n = params.L ** params.dim
+    if stream == "torch":
+        stream = default_stream()
+    _check(lib().sw_sweep_noalloc(ctypes.byref(params), ptr(spins, "torch.int8", n), sweep0, n_sweeps,
+                                  ptr(series, "torch.int64", 2 * n_sweeps), ptr(labels, "torch.int32", n),
+                                  ptr(err, "torch.int32", 1), stream))
 
 
 class Server:
