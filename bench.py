@@ -1,29 +1,39 @@
 #!/usr/bin/env python3
 """Benchmark of the Swendsen-Wang sweep on one MI355X.
 
-Default workload (the plain path): a 2D Ising lattice L=8192 at T_c and a 3D
-lattice L=256 at T=4.5115, periodic, J=1, seed 1, random +-1 starts.  One step
-is one sweep of both lattices (bonds, tile labelling, border merge, cluster
-flip).  `value` is site-updates per second over the K timed steps with the
-lattices resident in device memory.
+`value` (the plain path): a 2D Ising lattice L=8192 at T_c and a 3D lattice
+L=256 at T=4.5115, periodic, J=1, seed 1, random +-1 starts.  One step is one
+sweep of both lattices (bonds, tile labelling, border merge, cluster flip);
+`value` is site-updates per second over the K timed steps with the lattices
+resident in device memory.
 
-Extra objects on the JSON line:
-  roofline      the dominant kernel: algorithmic bytes per launch / its mean
-                duration from HIP events recorded around every launch in the
-                timed region, against the 8 TB/s HBM peak; `traffic` comes from
-                the rocprofv3 FETCH_SIZE / WRITE_SIZE summary in profiles/ when
-                it was taken on the current kernel sources, else null
-  cpu_baseline  the CPU oracle (single thread) on a bounded sample
-  batched       (--batched) 512 uneven replicas: batched phase launches replayed from a hipGraph
-                vs plain per-lattice launches, site-updates/s each
-  pcc           (--pcc) 64 replicas of 2D L=2048 with probability-changing cluster
-                feedback, batched: site-updates/s and the replicas' mean p
-  serving       (--serving) the first N jobs of the Poisson job stream (rate 50/s)
-                through the continuous-batching server: p50 / p99 latency and
-                aggregate site-updates/s
+Objects on the JSON line besides the contract's fields:
+  roofline           the dominant kernel (K1 on 8192^2): the method's bytes per
+                     site-update (2 B: read the int8 spin, write it back) times the
+                     sites of one launch, over its mean duration from HIP events
+                     recorded around every launch of the timed region, against the
+                     8 TB/s HBM peak.  `traffic` is the measured HBM bytes per launch
+                     from the rocprofv3 FETCH_SIZE / WRITE_SIZE summary in profiles/
+                     when it was taken on the current kernel sources, else null.
+                     The kernel's own design bytes (spin in, 16-bit label out) are
+                     reported beside it, and so is the whole sweep's rate in method
+                     bytes against the peak.
+  batched            the 512-replica workload (2D, L in {64..2048}, T in [2.0, 2.6]):
+                     500 sweeps batched (phase launches replayed from a hipGraph)
+                     and 500 sweeps of plain per-lattice launches, and their ratio
+  pcc                64 replicas of 2D L=2048 with probability-changing cluster
+                     feedback, batched: site-updates/s, the sweeps timed, and the
+                     replicas' mean p against the critical FK value 2 - sqrt(2)
+  serving            the first jobs of the Poisson job stream (rate 50/s) through
+                     the continuous-batching server: p50 / p99 latency and
+                     aggregate site-updates/s (the job count is stated)
+  cpu_baseline       the CPU oracle, single thread, on a bounded sample of the
+                     plain workload
+  cpu_baseline_batched  the oracle run replica-parallel on the machine's host cores
+                     (one process per core) on a sample of the batched workload
 
 Usage: python bench.py [--gpus 1] [--steps 200] [--warmup 20] [--no-cpu-baseline]
-       [--batched] [--copy-probe]
+       [--no-batched] [--no-pcc] [--no-serving] [--pcc-sweeps K] [--serving-jobs J]
 """
 from __future__ import annotations
 
@@ -40,12 +50,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SW site-updates/sec (batched vs plain) + % HBM roofline; p50/p99 job latency"
 HBM_PEAK_GBS = 8000.0
-# algorithmic HBM bytes per site of each kernel: what the kernel must move,
-# whatever it actually fetches
+# the method's HBM bytes per site-update: every sweep must read each int8 spin
+# and write it back, whatever the kernels move in between
+METHOD_BYTES_PER_SITE = 2.0
+# the bytes each kernel of this design must move per site (its own input and
+# output), reported beside the method's figure
 ALGO_BYTES_PER_SITE = {
     "k1_bond_label": 3.0,     # read the int8 spin, write the 16-bit tile label
     "k3_flip": 3.0,           # read the 16-bit tile label, write the int8 spin
 }
+HOST_CORES = 16               # the host-core share of one GPU on the measurement box
 KERNEL_SYMBOLS = {"k1_bond_label": "k1_kernel", "k2_merge": "k2_kernel", "k3_flip": "k3_kernel",
                   "k3_resolve": "k3a_kernel"}
 SOURCES = ["paper_0808_2109_amd/csrc/sw_device.hpp", "paper_0808_2109_amd/csrc/sw_kernels.hip"]
@@ -87,6 +101,37 @@ def cpu_baseline(workload, sweeps: int = 3):
             "host_cpu": model, "host_threads": os.cpu_count(),
             "sample": f"sweeps 0-{sweeps - 1} of each lattice of the workload (8192^2 at T_c and 256^3 at "
                       f"T=4.5115) from the seed-1 start, {sites} site-updates in {dt:.1f} s, single thread"}
+
+
+def _oracle_replica_sweeps(args):
+    """Worker: `sweeps` oracle sweeps of one replica from its start (site-updates done)."""
+    dim, L, seed, T, sweeps = args
+    import oracle
+
+    oracle.run(dim, L, seed, sweeps, T=T, record_series=False, keep_labels=False)
+    return L ** dim * sweeps
+
+
+def cpu_baseline_batched(workload, sweeps: int = 3, cores: int = HOST_CORES):
+    """The oracle on the batched workload, replicas spread over `cores` worker
+    processes (the replicas are independent); started before anything touches
+    the GPU, with the spawn method."""
+    import multiprocessing as mp
+
+    import oracle
+
+    oracle.build(force=not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")))
+    cores = max(1, min(cores, os.cpu_count() or 1))
+    jobs = [(r.dim, r.L, r.seed, r.T, sweeps) for r in workload.replicas]
+    jobs.sort(key=lambda j: -j[1])                 # largest first: better balance
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        done = sum(pool.map(_oracle_replica_sweeps, jobs, chunksize=1))
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "site-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"sweeps 0-{sweeps - 1} of all {len(jobs)} replicas of the batched workload from their "
+                      f"starts, one process per core, {done} site-updates in {dt:.1f} s"}
 
 
 def traffic_from_profile(kernel_key: str, launch_sites: int):
@@ -234,12 +279,14 @@ def copy_probe():
 
 
 def run_batched(swgpu, workloads, sweeps_batched: int, sweeps_plain: int):
+    """The 512-replica workload: batched sweeps (graph replay) against plain
+    per-lattice launches of the same replicas from the same state."""
     import torch
 
     wl = workloads.batched()
     params = [swgpu.params_from_replica(r) for r in wl.replicas]
     sites = sum(r.nsites for r in wl.replicas)
-    out = {"replicas": len(params), "sites": sites}
+    out = {"workload": wl.name, "replicas": len(params), "sites": sites}
     # the timed sweeps run as calls of `chunk` sweeps, the way a driver loop
     # calls sw_sweep; the first call of that size (untimed) captures the
     # hipGraph that the timed calls replay
@@ -248,6 +295,8 @@ def run_batched(swgpu, workloads, sweeps_batched: int, sweeps_plain: int):
         lat.set_mode(swgpu.SW_MODE_BATCHED)
         lat.sweep(10)                       # warm-up: the tuner times the current state
         lat.autotune(sweeps=2)
+        out["tile_shape"] = list(swgpu.tile_shapes(2)[lat.tile_shape(0)])
+        out["workgroups_per_cu"] = lat.batch_grid()
         lat.sweep(chunk)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -268,36 +317,53 @@ def run_batched(swgpu, workloads, sweeps_batched: int, sweeps_plain: int):
         dt = time.perf_counter() - t0
         out["plain"] = {"site_updates_per_s": sites * sweeps_plain / dt, "sweeps": sweeps_plain, "seconds": dt}
     out["batched_over_plain"] = out["batched"]["site_updates_per_s"] / out["plain"]["site_updates_per_s"]
+    out["method_bytes_frac_of_hbm_peak"] = (out["batched"]["site_updates_per_s"] * METHOD_BYTES_PER_SITE
+                                            / (HBM_PEAK_GBS * 1e9))
     return out
 
 
-def run_pcc(swgpu, workloads, sweeps: int):
-    """Probability-changing cluster feedback: 64 replicas of 2D L=2048, batched."""
+def run_pcc(swgpu, workloads, sweeps: int, replicas: int = 64, trace_every: int = 0):
+    """Probability-changing cluster feedback: `replicas` replicas of 2D L=2048, batched."""
     import torch
 
-    wl = workloads.pcc(sweeps=sweeps)
+    wl = workloads.pcc(n=replicas, sweeps=sweeps)
     params = [swgpu.params_from_replica(r) for r in wl.replicas]
     sites = sum(r.nsites for r in wl.replicas)
     stream = torch.cuda.Stream()
     chunk = max(1, min(100, sweeps))        # timed as calls of `chunk` sweeps; the warm-up call builds their graph
+    trace = []
     with swgpu.Lattice(params, stream=ctypes.c_void_p(stream.cuda_stream)) as lat:
         lat.set_mode(swgpu.SW_MODE_BATCHED)
         lat.sweep(chunk)
         torch.cuda.synchronize()
+        warm = chunk
         t0 = time.perf_counter()
         done = 0
         while done < sweeps:
             lat.sweep(min(chunk, sweeps - done))
             done += min(chunk, sweeps - done)
+            if trace_every and (done % trace_every == 0 or done == sweeps):
+                torch.cuda.synchronize()
+                t_pause = time.perf_counter()
+                ps = [lat.state(r)[1] for r in range(len(params))]
+                m = sum(ps) / len(ps)
+                trace.append({"sweep": warm + done, "p_mean": m,
+                              "p_std": (sum((p - m) ** 2 for p in ps) / len(ps)) ** 0.5})
+                log(f"pcc: sweep {warm + done}: mean p {m:.5f}")
+                t0 += time.perf_counter() - t_pause     # reading p is not part of the timed work
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         ps = [lat.state(r)[1] for r in range(len(params))]
     n = len(ps)
     mean = sum(ps) / n
-    return {"workload": wl.name, "replicas": n, "sites": sites, "sweeps": sweeps, "seconds": dt,
-            "site_updates_per_s": sites * sweeps / dt, "p_mean": mean,
-            "p_std": (sum((p - mean) ** 2 for p in ps) / n) ** 0.5,
-            "p_c_fk_2d": 1.0 - 1.0 / (1.0 + 2.0 ** 0.5)}
+    out = {"workload": wl.name, "replicas": n, "sites": sites, "sweeps_timed": sweeps,
+           "sweeps_total": warm + sweeps, "seconds": dt,
+           "site_updates_per_s": sites * sweeps / dt, "p_mean": mean,
+           "p_std": (sum((p - mean) ** 2 for p in ps) / n) ** 0.5,
+           "p_c_fk_2d": 2.0 - 2.0 ** 0.5}
+    if trace:
+        out["p_trajectory"] = trace
+    return out
 
 
 def run_serving(swgpu, workloads, n_jobs: int, budget_gib: float, slots: int, tick: int, rate: float = 50.0):
@@ -339,10 +405,48 @@ def run_serving(swgpu, workloads, n_jobs: int, budget_gib: float, slots: int, ti
     def pct(q):
         return lat[min(len(lat) - 1, int(q * len(lat)))] if lat else None
 
-    return {"jobs": n_jobs, "done": st["done"], "rejected": st["rejected"], "rate_per_s": rate,
+    return {"jobs": n_jobs, "of_stream": 2000, "done": st["done"], "rejected": st["rejected"], "rate_per_s": rate,
             "seconds": wall, "site_updates": st["site_updates"], "site_updates_per_s": st["site_updates"] / wall,
             "p50_latency_s": pct(0.5), "p99_latency_s": pct(0.99), "hbm_budget_gib": budget_gib,
             "slots": slots, "sweeps_per_tick": tick}
+
+
+def run_plain(swgpu, workloads, steps: int, warmup: int, autotune: bool):
+    """The plain workload: one sweep of each lattice per step, HIP-event kernel times."""
+    import torch
+
+    wl = workloads.plain()
+    # one stream for both lattices: their sweeps run one after the other, so
+    # every kernel's event-timed duration is its own, not shared with the other
+    # lattice's kernels
+    stream = torch.cuda.Stream()
+    handle = ctypes.c_void_p(stream.cuda_stream)
+    lats = [swgpu.Lattice(swgpu.params_from_replica(rep), stream=handle) for rep in wl.replicas]
+    log(f"workload {wl.name}: {[r.nsites for r in wl.replicas]} sites, warmup {warmup}, steps {steps}")
+    # warm up first: the autotuner times the tile shapes on a copy of the
+    # current (equilibrated) state
+    for _ in range(warmup):
+        for lat in lats:
+            lat.sweep(1)
+    torch.cuda.synchronize()
+    if autotune:
+        for lat in lats:
+            lat.autotune(sweeps=3)
+    shapes = [swgpu.tile_shapes(r.dim)[lat.tile_shape(0)] for r, lat in zip(wl.replicas, lats)]
+    torch.cuda.synchronize()
+    for lat in lats:
+        lat.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for lat in lats:
+            lat.sweep(1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    timings = [lat.timing() for lat in lats]
+    for lat in lats:
+        lat.close()
+    return wl, shapes, dt, timings
 
 
 def main():
@@ -352,19 +456,24 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--batched", action="store_true", help="also time the 512-replica batched workload")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-replica batched workload")
     ap.add_argument("--batched-sweeps", type=int, default=500)
+    ap.add_argument("--batched-plain-sweeps", type=int, default=500)
     ap.add_argument("--copy-probe", action="store_true")
-    ap.add_argument("--pcc", action="store_true", help="also time the 64 x 2048^2 PCC feedback workload")
-    ap.add_argument("--pcc-sweeps", type=int, default=200)
-    ap.add_argument("--serving", action="store_true", help="also run a Poisson job stream through the server")
-    ap.add_argument("--serving-jobs", type=int, default=40)
-    ap.add_argument("--serving-budget-gib", type=float, default=64.0)
+    ap.add_argument("--no-pcc", action="store_true", help="skip the 64 x 2048^2 PCC feedback workload")
+    ap.add_argument("--pcc-sweeps", type=int, default=1000)
+    ap.add_argument("--pcc-trace-every", type=int, default=0,
+                    help="record the replicas' mean p every this many timed sweeps")
+    ap.add_argument("--no-serving", action="store_true", help="skip the Poisson job stream through the server")
+    ap.add_argument("--serving-jobs", type=int, default=16)
+    ap.add_argument("--serving-budget-gib", type=float, default=200.0)
     ap.add_argument("--serving-slots", type=int, default=64)
     ap.add_argument("--serving-load", type=float, default=None,
-                    help="with --serving: run the same jobs again with arrivals scaled so that the offered load is "
-                         "this fraction of the throughput the first (saturated) run measured")
+                    help="run the same jobs again with arrivals scaled so that the offered load is this "
+                         "fraction of the throughput the first (saturated) run measured")
     ap.add_argument("--serving-tick", type=int, default=25)
+    ap.add_argument("--only", choices=["pcc", "serving", "batched"], default=None,
+                    help="run only this workload (its JSON object alone)")
     ap.add_argument("--summarize", metavar="PROF_DIR",
                     help="write the profiles/ summaries from rocprofv3 runs under PROF_DIR (no GPU needed)")
     ap.add_argument("--summary-commands", nargs=3, metavar=("TRACE", "PMC", "COPY"), default=("?", "?", "?"))
@@ -378,45 +487,44 @@ def main():
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
               file=sys.stderr)
         sys.exit(2)
+
+    from paper_0808_2109_amd import workloads
+
+    # the CPU legs run first, before anything touches the GPU (their worker
+    # processes are started from a process that has not initialised it)
+    cpu = {}
+    if not args.no_cpu_baseline and args.only is None and not args.copy_probe:
+        log("timing the CPU oracle ...")
+        cpu["cpu_baseline"] = cpu_baseline(workloads.plain())
+        if not args.no_batched:
+            log("timing the CPU oracle on the batched workload, replica-parallel ...")
+            cpu["cpu_baseline_batched"] = cpu_baseline_batched(workloads.batched())
+
     if args.copy_probe:
         copy_probe()
         return
 
     import torch
-    from paper_0808_2109_amd import swgpu, workloads
+    from paper_0808_2109_amd import swgpu
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    wl = workloads.plain()
-    # one stream for both lattices: their sweeps run one after the other, so
-    # every kernel's event-timed duration is its own, not shared with the other
-    # lattice's kernels
-    stream = torch.cuda.Stream()
-    handle = ctypes.c_void_p(stream.cuda_stream)
-    lats = [swgpu.Lattice(swgpu.params_from_replica(rep), stream=handle) for rep in wl.replicas]
-    log(f"workload {wl.name}: {[r.nsites for r in wl.replicas]} sites, warmup {args.warmup}, steps {args.steps}")
-    # warm up first: the autotuner times the tile shapes on a copy of the
-    # current (equilibrated) state
-    for _ in range(args.warmup):
-        for lat in lats:
-            lat.sweep(1)
-    torch.cuda.synchronize()
-    if not args.no_autotune:
-        for lat in lats:
-            lat.autotune(sweeps=3)
-    shapes = [swgpu.tile_shapes(r.dim)[lat.tile_shape(0)] for r, lat in zip(wl.replicas, lats)]
-    torch.cuda.synchronize()
-    for lat in lats:
-        lat.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        for lat in lats:
-            lat.sweep(1)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    timings = [lat.timing() for lat in lats]
+
+    if args.only:
+        if args.only == "pcc":
+            res = run_pcc(swgpu, workloads, args.pcc_sweeps, trace_every=args.pcc_trace_every)
+        elif args.only == "batched":
+            res = run_batched(swgpu, workloads, args.batched_sweeps, args.batched_plain_sweeps)
+        else:
+            res = {"serving": run_serving(swgpu, workloads, args.serving_jobs, args.serving_budget_gib,
+                                          args.serving_slots, args.serving_tick)}
+            if args.serving_load:
+                res["serving_at_load"] = serving_at_load(swgpu, workloads, args, res["serving"])
+        print(json.dumps({"only": args.only, **(res if args.only == "serving" else {args.only: res})}), flush=True)
+        return
+
+    wl, shapes, dt, timings = run_plain(swgpu, workloads, args.steps, args.warmup, not args.no_autotune)
     sites = sum(r.nsites for r in wl.replicas)
     value = sites * args.steps / dt
     log(f"{args.steps} steps in {dt:.4f} s -> {value:.4e} site-updates/s")
@@ -429,18 +537,22 @@ def main():
             if n == 0 or key not in ALGO_BYTES_PER_SITE:
                 continue
             avg_ms = ms / n
-            algo = ALGO_BYTES_PER_SITE[key] * rep.nsites
             kernels[f"{key}:{tag}"] = {"kernel": key, "lattice": tag, "sites": rep.nsites, "mean_us": avg_ms * 1e3,
-                                       "total_ms": ms, "launches": n,
-                                       "algo_bytes_per_launch": algo,
-                                       "achieved_GBs": algo / (avg_ms * 1e-3) / 1e9}
+                                       "total_ms": ms, "launches": n}
     dom = max(kernels.values(), key=lambda k: k["total_ms"])
     log("kernels:", json.dumps(kernels, indent=1))
     traffic = traffic_from_profile(f"{dom['kernel']}:{dom['lattice']}", dom["sites"])
+    secs = dom["mean_us"] * 1e-6
+    achieved = METHOD_BYTES_PER_SITE * dom["sites"] / secs / 1e9
+    design = ALGO_BYTES_PER_SITE[dom["kernel"]] * dom["sites"] / secs / 1e9
     roofline = {"bound": "hbm", "kernel": f"{KERNEL_SYMBOLS[dom['kernel']]} ({dom['lattice']})",
-                "achieved": dom["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": dom["achieved_GBs"] / HBM_PEAK_GBS, "traffic": traffic,
-                "algo_bytes_per_site": ALGO_BYTES_PER_SITE[dom["kernel"]], "mean_launch_us": dom["mean_us"]}
+                "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "method_bytes_per_site": METHOD_BYTES_PER_SITE, "mean_launch_us": dom["mean_us"],
+                "sites_per_launch": dom["sites"],
+                "kernel_design_bytes_per_site": ALGO_BYTES_PER_SITE[dom["kernel"]],
+                "kernel_design_frac": design / HBM_PEAK_GBS,
+                "sweep_method_bytes_frac": value * METHOD_BYTES_PER_SITE / (HBM_PEAK_GBS * 1e9)}
 
     result = {
         "metric": METRIC,
@@ -462,32 +574,35 @@ def main():
                    "kernel_means_us": {k: round(v["mean_us"], 2) for k, v in kernels.items()}},
         "roofline": roofline,
     }
-    for lat in lats:
-        lat.close()
-    if args.batched:
-        result["batched"] = run_batched(swgpu, workloads, args.batched_sweeps, max(args.batched_sweeps // 10, 2))
-    if args.pcc:
-        result["pcc"] = run_pcc(swgpu, workloads, args.pcc_sweeps)
-    if args.serving:
+    if not args.no_batched:
+        log("batched workload ...")
+        result["batched"] = run_batched(swgpu, workloads, args.batched_sweeps, args.batched_plain_sweeps)
+    if not args.no_pcc:
+        log("pcc workload ...")
+        result["pcc"] = run_pcc(swgpu, workloads, args.pcc_sweeps, trace_every=args.pcc_trace_every)
+    if not args.no_serving:
+        log("serving workload ...")
         result["serving"] = run_serving(swgpu, workloads, args.serving_jobs, args.serving_budget_gib,
                                         args.serving_slots, args.serving_tick)
         if args.serving_load:
-            # same jobs (the generator draws the same numbers at any rate), arrivals
-            # spaced so that the offered site-updates/s is the asked fraction of capacity
-            cap = result["serving"]["site_updates_per_s"]
-            jobs = workloads.serving(n_jobs=args.serving_jobs)
-            work = sum(j.replica.nsites * j.sweeps for j in jobs) / len(jobs)
-            rate = args.serving_load * cap / work
-            log(f"serving at {args.serving_load:.0%} of {cap:.3e} site-updates/s: {rate:.3f} jobs/s")
-            res = run_serving(swgpu, workloads, args.serving_jobs, args.serving_budget_gib, args.serving_slots,
-                              args.serving_tick, rate=rate)
-            res.update({"load": args.serving_load, "capacity_site_updates_per_s": cap,
-                        "mean_site_updates_per_job": work})
-            result["serving_at_load"] = res
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle ...")
-        result["cpu_baseline"] = cpu_baseline(wl)
+            result["serving_at_load"] = serving_at_load(swgpu, workloads, args, result["serving"])
+    result.update(cpu)
     print(json.dumps(result), flush=True)
+
+
+def serving_at_load(swgpu, workloads, args, saturated):
+    """The same jobs (the generator draws the same numbers at any rate), arrivals
+    spaced so that the offered site-updates/s is the asked fraction of the
+    capacity the saturated run measured."""
+    cap = saturated["site_updates_per_s"]
+    jobs = workloads.serving(n_jobs=args.serving_jobs)
+    work = sum(j.replica.nsites * j.sweeps for j in jobs) / len(jobs)
+    rate = args.serving_load * cap / work
+    log(f"serving at {args.serving_load:.0%} of {cap:.3e} site-updates/s: {rate:.3f} jobs/s")
+    res = run_serving(swgpu, workloads, args.serving_jobs, args.serving_budget_gib, args.serving_slots,
+                      args.serving_tick, rate=rate)
+    res.update({"load": args.serving_load, "capacity_site_updates_per_s": cap, "mean_site_updates_per_job": work})
+    return res
 
 
 if __name__ == "__main__":

@@ -160,8 +160,8 @@ int sw_get_series(sw_lattice* h, int32_t replica, int64_t* host_buf, int64_t cap
 /* Copy the N spins of a replica to host memory (cap >= N).  Synchronises. */
 int sw_get_spins(sw_lattice* h, int32_t replica, int8_t* host_buf, int64_t cap);
 
-/* Copy the N canonical labels of the last sweep (needs SW_KEEP_LABELS or SW_PCC,
- * and at least one sweep done).  Synchronises. */
+/* Copy the N canonical labels of the last sweep (needs SW_KEEP_LABELS and at
+ * least one sweep done).  Synchronises. */
 int sw_get_labels(sw_lattice* h, int32_t replica, int32_t* host_buf, int64_t cap);
 
 /* Current sweep index (sweeps done), bond probability p and threshold thr of a

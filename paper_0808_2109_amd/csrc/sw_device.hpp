@@ -77,6 +77,8 @@ struct SwRep {
     int64_t* series;            // 2 * series_cap
     int64_t* acc;               // 2 scratch accumulators (measure)
     uint64_t* cand;             // PCC: dim * N candidate marks (tag << 32 | ~slot)
+    uint64_t* cov;              // PCC: per tile, 2 * ft entries of two words: the coverage of each
+                                // border root within the tile (K1 -> K3a)
     uint32_t* bmp;              // PCC: dim * L^(dim-1) * ceil(L/32) coverage bitmaps
     int32_t* pflag;             // PCC: percolation flag of the current sweep
     int32_t* perc_trace;        // PCC: trace_cap flags
@@ -433,7 +435,23 @@ struct K1Cfg {
     static_assert(C::NR == 64, "64 rows per tile");
 };
 
+// PCC coverage of the tile's border roots, indexed by rank (the number of
+// border roots before it in the border bitmap): a holds the x columns the
+// cluster occupies in the tile (bit lx); b the rows (2D: bit ly; 3D: bit ly
+// and bit TY + lz)
+template <class C, bool PCC>
+struct K1Cov {
+};
+
 template <class C>
+struct K1Cov<C, true> {
+    static constexpr int CAP = 2 * C::FT;   // a border root has a site on a near face or a far-face link
+    unsigned long long a[CAP];
+    unsigned long long b[CAP];
+    int32_t pre[C::FBW];                    // border roots before each bitmap word
+};
+
+template <class C, bool PCC>
 struct alignas(16) K1Smem {
     int32_t par[C::TS];    // parents of the run starts (tile-local site indices)
     uint32_t FB[C::FBW];   // border flag of every tile-local root
@@ -441,6 +459,7 @@ struct alignas(16) K1Smem {
     uint64_t SS[C::NR];    // run starts of the rows
     uint32_t XF[2];        // open links leaving through the far x face (bit = row)
     uint32_t ring[kBlock / 64][kRing];   // per-wave queue of pending unions
+    K1Cov<C, PCC> cov;
 };
 
 // spins of 4 / 16 sites -> their up bits (a spin is up when it is positive)
@@ -524,9 +543,10 @@ __device__ __forceinline__ uint32_t part_bonds_coarse(uint32_t eq, uint32_t lbas
 }
 
 // Threads beyond K1Cfg<C>::NT (a workgroup sized for a larger tile) take part
-// in the barriers only.
-template <class C>
-__device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<C>& sm, bool measure,
+// in the barriers only.  With PCC the tile also records, for each border
+// root, the columns and rows its cluster occupies in the tile.
+template <class C, bool PCC>
+__device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<C, PCC>& sm, bool measure,
                         int64_t& e_acc, int64_t& m_acc)
 {
     using K = K1Cfg<C>;
@@ -575,6 +595,9 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
     for (int w = tid; w < C::FBW; w += blockDim.x) sm.FB[w] = 0;
     for (int k = 4 * tid; k < C::TS; k += 4 * (int)blockDim.x)
         *reinterpret_cast<uint4*>(&sm.par[k]) = make_uint4((uint32_t)k, (uint32_t)k + 1u, (uint32_t)k + 2u, (uint32_t)k + 3u);
+    if constexpr (PCC) {
+        for (int k = tid; k < K1Cov<C, true>::CAP; k += blockDim.x) sm.cov.a[k] = sm.cov.b[k] = 0ull;
+    }
     __syncthreads();
 
     // 2) bonds of the row's own links (x, d), each thread those of its part
@@ -807,6 +830,84 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
     }
     __syncthreads();
 
+    // 4b) PCC: the columns and rows each border cluster occupies in the tile.
+    //    A cluster that covers every coordinate of an axis meets the
+    //    hyperplane x_a = 0 and so touches a near face of some tile: only
+    //    border clusters can span.  Each run start of a border cluster ORs its
+    //    run's columns and its row into the cluster's entry; a thread merges
+    //    consecutive runs of one cluster before the LDS atomics.
+    // (a batched launch runs this variant for every replica of a batch that
+    // holds a PCC replica: only PCC replicas have coverage entries)
+    if constexpr (PCC) if (R.flags & FLAG_PCC) {
+        using CV = K1Cov<C, true>;
+        constexpr int WPL = (C::FBW + 63) / 64;         // bitmap words per lane of wave 0
+        if (tid < 64) {
+            int cnt[WPL];
+            int tot = 0;
+#pragma unroll
+            for (int k = 0; k < WPL; ++k) {
+                const int w = tid * WPL + k;
+                cnt[k] = (w < C::FBW) ? __popc(sm.FB[w]) : 0;
+                tot += cnt[k];
+            }
+            int inc = tot;
+            for (int off = 1; off < 64; off <<= 1) {
+                const int v = __shfl_up(inc, off, 64);
+                if (tid >= off) inc += v;
+            }
+            int ex = inc - tot;
+#pragma unroll
+            for (int k = 0; k < WPL; ++k) {
+                const int w = tid * WPL + k;
+                if (w < C::FBW) sm.cov.pre[w] = ex;
+                ex += cnt[k];
+            }
+        }
+        __syncthreads();
+        if (partok) {
+            const unsigned long long rowb = (C::D == 3) ? ((1ull << ly) | (1ull << (C::TY + lz))) : (1ull << ly);
+            uint32_t m = ss16;
+            int cr = -1;
+            unsigned long long ca = 0, cb = 0;
+            while (m) {
+                const int j = __builtin_ctz(m);
+                m &= m - 1u;
+                const int x = xp + j;
+                const uint32_t root = (uint32_t)lds_load(&sm.par[rowk + x]);   // the walk left the root here
+                const uint32_t fw = sm.FB[root >> 5];
+                if (!((fw >> (root & 31u)) & 1u)) continue;
+                const int rank = sm.cov.pre[root >> 5] + __popc(fw & ((1u << (root & 31u)) - 1u));
+                if (rank >= CV::CAP) {
+                    flag_error(R, ERR_TILE_LABEL);
+                    continue;
+                }
+                const uint64_t later = SS & ~low_bits(x + 1);
+                const int xe = later ? __builtin_ctzll(later) - 1 : g.wx - 1;   // last site of the run
+                if (rank != cr) {
+                    if (cr >= 0) {
+                        atomicOr(&sm.cov.a[cr], ca);
+                        atomicOr(&sm.cov.b[cr], cb);
+                    }
+                    cr = rank;
+                    ca = cb = 0;
+                }
+                ca |= low_bits(xe + 1) & ~low_bits(x);
+                cb |= rowb;
+            }
+            if (cr >= 0) {
+                atomicOr(&sm.cov.a[cr], ca);
+                atomicOr(&sm.cov.b[cr], cb);
+            }
+        }
+        __syncthreads();
+        const int nb = sm.cov.pre[C::FBW - 1] + __popc(sm.FB[C::FBW - 1]);
+        unsigned long long* dst = reinterpret_cast<unsigned long long*>(R.cov) + (size_t)t * (2 * CV::CAP);
+        for (int k = tid; k < nb && k < CV::CAP; k += blockDim.x) {
+            dst[2 * k] = sm.cov.a[k];
+            dst[2 * k + 1] = sm.cov.b[k];
+        }
+    }
+
     // 5) the border bitmap and the far x face's crossing bits; every border
     //    root starts its own tree in the global union-find
     for (int w = tid; w < C::FBW; w += blockDim.x) R.fbits[(size_t)t * C::FBW + w] = sm.FB[w];
@@ -967,103 +1068,6 @@ __device__ void k2_tile(const SwRep& R, int t, K2Smem<C>& sm)
     __syncthreads();
 }
 
-// --------------------------------------------------------------------------
-// K3a: border roots and the tile's flip bitmap, one wave per tile.  The roots
-// in the tile's border bitmap are compacted into a list; each lane takes one
-// at a time, finds its cluster root (the smallest site index of the cluster:
-// the label identity that the min-label rule of Sec. II.B converges to),
-// keeps it as parent when labels are written, and records the cluster's flip
-// bit.  Each lane also draws the flip bits of one tile row: an interior root
-// is its own cluster's label, so its bit is the one drawn for its own site.
-// The result is one bit per tile-local site, meaningful at the tile roots.
-// --------------------------------------------------------------------------
-template <class C>
-struct K3aSmem {
-    uint16_t list[2 * C::FT];    // the tile's border roots (each has a site on a face)
-    uint32_t BF[C::FBW];         // flip bits of the border roots
-    uint32_t FBt[C::FBW];        // the border-root bitmap
-    int cnt;
-};
-
-template <class C>
-__device__ void k3a_tile(const SwRep& R, int t, uint32_t s, K3aSmem<C>& sm)
-{
-    constexpr int CAP = 2 * C::FT;
-    const int lane = threadIdx.x & 63;
-    const TileGeo g = tile_geo<C>(R, t);
-    const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
-    const bool keep = R.lab32 != nullptr || (R.flags & FLAG_PCC) != 0;
-    static_assert(C::NR == 64, "one tile row per lane");
-    if (lane == 0) sm.cnt = 0;
-    for (int w = lane; w < C::FBW; w += 64) sm.BF[w] = 0;
-    wave_lds_sync();
-    for (int w = lane; w < C::FBW; w += 64) {
-        uint32_t m = R.fbits[(size_t)t * C::FBW + w];
-        sm.FBt[w] = m;
-        if (!m) continue;
-        int pos = atomicAdd(&sm.cnt, __popc(m));
-        while (m) {
-            const int b = __ffs(m) - 1;
-            m &= m - 1u;
-            if (pos < CAP) sm.list[pos] = (uint16_t)(w * 32 + b);
-            ++pos;
-        }
-    }
-    wave_lds_sync();
-    uint64_t rf = 0;   // flip bits of this lane's row
-    {
-        const int ly = lane % C::TY, lz = lane / C::TY;
-        if (ly < g.wy && lz < g.wz)
-            rf = row_flips((uint32_t)g.x0 + (uint32_t)R.L * ((uint32_t)(g.y0 + ly) + (uint32_t)R.L * (uint32_t)(g.z0 + lz)),
-                           g.wx, s, k0, k1);
-    }
-    const int nb = sm.cnt;
-    if (nb > CAP && lane == 0) flag_error(R, ERR_TILE_LABEL);   // more border roots than face sites
-    const int nl = min(nb, CAP);
-    // two list entries per lane and step (i and i + 64), their finds together
-    for (int i = lane; i < nl; i += 128) {
-        const bool two = i + 64 < nl;
-        uint32_t lr[2], gi[2], root[2];
-        lr[0] = sm.list[i];
-        lr[1] = two ? sm.list[i + 64] : lr[0];
-#pragma unroll
-        for (int e = 0; e < 2; ++e) gi[e] = local_to_global<C>(lr[e], g.x0, g.y0, g.z0, R.L);
-        if (gi[0] >= R.N || gi[1] >= R.N) {
-            flag_error(R, ERR_TILE_LABEL);
-            continue;
-        }
-        root[0] = gi[0];
-        root[1] = gi[1];
-        ro_find2(R, root[0], root[1]);
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            if (e == 1 && !two) break;
-            if (keep && root[e] != gi[e]) R.par[gi[e]] = (int32_t)root[e];
-            if (flip_bit(root[e], s, k0, k1)) atomicOr(&sm.BF[lr[e] >> 5], 1u << (lr[e] & 31u));
-        }
-    }
-    wave_lds_sync();
-    constexpr int WPR = C::TX / 32;   // bitmap words per row
-#pragma unroll
-    for (int k = 0; k < WPR; ++k) {
-        const int w = lane * WPR + k;
-        const uint32_t fb = sm.FBt[w];
-        R.bflip[(size_t)t * C::FBW + w] = (fb & sm.BF[w]) | (~fb & (uint32_t)(rf >> (32 * k)));
-    }
-}
-
-// --------------------------------------------------------------------------
-// K3b: cluster flip.  Every site takes the flip bit that K3a recorded for its
-// tile root and gets its cluster's new spin.  Optionally writes the final
-// labels and marks percolation coverage (PCC).
-// --------------------------------------------------------------------------
-template <class C>
-struct K3Smem {
-    uint32_t FL[C::FBW];         // flip bit of every tile root (from K3a)
-    uint32_t FBt[C::FBW];        // the tile's border-root bitmap (labels and PCC only)
-    uint32_t wor[kK3Block / 64]; // per-wave word for combining coverage marks
-};
-
 // atomicOr(addr, bits) for every lane with `pending`, combined over the wave:
 // lanes with the same target word OR their bits into the wave's LDS word and
 // one of them makes the global atomic.  All lanes of the wave must call it.
@@ -1090,86 +1094,186 @@ __device__ __forceinline__ void wave_or(uint32_t* addr, uint32_t bits, bool pend
     }
 }
 
-// PCC coverage: if the cluster `root` is a candidate of axis a in this sweep,
-// the bit of coordinate crd of its axis-a bitmap (all lanes of the wave call it)
+// --------------------------------------------------------------------------
+// K3a: border roots and the tile's flip bitmap, one wave per tile.  The roots
+// in the tile's border bitmap are compacted into a list; each lane takes one
+// at a time, finds its cluster root (the smallest site index of the cluster:
+// the label identity that the min-label rule of Sec. II.B converges to),
+// keeps it as parent when labels are written, and records the cluster's flip
+// bit.  Each lane also draws the flip bits of one tile row: an interior root
+// is its own cluster's label, so its bit is the one drawn for its own site.
+// The result is one bit per tile-local site, meaningful at the tile roots.
+// --------------------------------------------------------------------------
 template <class C>
-__device__ __forceinline__ void pcc_mark(const SwRep& R, uint32_t root, bool valid, const uint32_t crd[3], uint64_t tag,
-                                         uint32_t bw, uint32_t nslots, uint32_t* wscr)
+struct K3aSmem {
+    uint16_t list[2 * C::FT];    // the tile's border roots in bitmap order (each has a site on a face)
+    uint32_t root[2 * C::FT];    // their cluster roots (PCC coverage marks)
+    uint32_t BF[C::FBW];         // flip bits of the border roots
+    uint32_t FBt[C::FBW];        // the border-root bitmap
+    uint32_t wor;                // word for combining coverage marks over the wave
+};
+
+// PCC coverage marks (extension rule, Sec. III): every border root of the
+// tile whose cluster is a candidate of axis a in this sweep (it meets the
+// hyperplane x_a = 0; k_cand_tile gave it a slot) ORs the axis-a coordinates
+// its tile cluster occupies (K1's coverage entry, shifted to the tile's
+// origin) into the slot's bitmap.  Marks of one bitmap word are combined over
+// the wave before the global atomic; every lane runs the same iterations.
+template <class C>
+__device__ void k3a_coverage(const SwRep& R, int t, uint32_t s, const TileGeo& g, int nl, K3aSmem<C>& sm)
 {
+    constexpr int CAP = 2 * C::FT;
+    const int lane = threadIdx.x & 63;
+    const uint64_t tag = (uint64_t)(s + 1u) << 32;
+    const uint32_t L = (uint32_t)R.L;
+    const uint32_t bw = (L + 31u) / 32u;
+    const uint32_t nslots = (C::D == 3) ? L * L : L;
+    const unsigned long long* cov = reinterpret_cast<const unsigned long long*>(R.cov) + (size_t)t * (2 * CAP);
+    wave_lds_sync();
+    for (int base = 0; base < nl; base += 64) {
+        const int k = base + lane;
+        const bool valid = k < nl;
+        const uint32_t root = valid ? sm.root[k] : 0u;
+        const unsigned long long ca = valid ? cov[2 * k] : 0ull, cb = valid ? cov[2 * k + 1] : 0ull;
 #pragma unroll
-    for (int a = 0; a < C::D; ++a) {
-        bool pending = false;
-        uint32_t* word = nullptr;
-        if (valid) {
-            const uint64_t c = R.cand[(size_t)a * R.N + root];
-            if ((c & 0xFFFFFFFF00000000ull) == tag) {
-                const uint32_t slot = ~(uint32_t)c;
-                if (slot < nslots) {
-                    word = R.bmp + ((size_t)a * nslots + slot) * bw + (crd[a] >> 5);
-                    pending = true;
-                } else {
-                    flag_error(R, ERR_SLOT);
+        for (int a = 0; a < C::D; ++a) {
+            bool cand = false;
+            uint32_t slot = 0;
+            if (valid && root < R.N) {
+                const uint64_t c = R.cand[(size_t)a * R.N + root];
+                if ((c & 0xFFFFFFFF00000000ull) == tag) {
+                    slot = ~(uint32_t)c;
+                    if (slot < nslots) cand = true;
+                    else flag_error(R, ERR_SLOT);
                 }
             }
+            // this cluster's axis-a coordinates in the tile, from the tile's origin on
+            uint64_t bits;
+            uint32_t c0;
+            if (a == 0) {
+                bits = ca & low_bits(C::TX);
+                c0 = (uint32_t)g.x0;
+            } else if (a == 1) {
+                bits = cb & low_bits(C::TY);
+                c0 = (uint32_t)g.y0;
+            } else {
+                bits = (cb >> C::TY) & low_bits(C::TZ);
+                c0 = (uint32_t)g.z0;
+            }
+            // tile origins are multiples of the extent (32 / 64 in x, 64 in 2D y,
+            // 8 in 3D y and z), so the shifted bits stay within two words
+            const uint64_t sb = bits << (c0 & 31u);
+            uint32_t* row = R.bmp + ((size_t)a * nslots + slot) * bw + (c0 >> 5);
+            const uint32_t lo = (uint32_t)sb, hi = (uint32_t)(sb >> 32);
+            wave_or(row, lo, cand && lo != 0u, &sm.wor);
+            wave_or(row + 1, hi, cand && hi != 0u, &sm.wor);
         }
-        wave_or(word, 1u << (crd[a] & 31u), pending, wscr);
     }
 }
 
-// PCC coverage marks of a quad of sites (x .. x+3 of one row): the candidate
-// words of all four sites and axes are loaded together, and marks of an axis
-// that hit the same bitmap word (the quad shares its x word and its y, z) are
-// merged before the wave-combined atomics (all lanes of the wave call it)
 template <class C>
-__device__ __forceinline__ void pcc_quad(const SwRep& R, const uint32_t root[4], bool valid, uint32_t x, uint32_t y,
-                                         uint32_t z, uint64_t tag, uint32_t bw, uint32_t nslots, uint32_t* wscr)
+__device__ void k3a_tile(const SwRep& R, int t, uint32_t s, K3aSmem<C>& sm)
 {
-    uint64_t c[C::D][4];
+    constexpr int CAP = 2 * C::FT;
+    const int lane = threadIdx.x & 63;
+    const TileGeo g = tile_geo<C>(R, t);
+    const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
+    const bool keep = R.lab32 != nullptr;
+    const bool pcc = (R.flags & FLAG_PCC) != 0;
+    static_assert(C::NR == 64, "one tile row per lane");
+    // the border roots in bitmap order (rank order, the order of K1's
+    // coverage entries): lane l takes words [l * WPL, (l + 1) * WPL)
+    constexpr int WPL = (C::FBW + 63) / 64;
+    uint32_t mw[WPL];
+    int tot = 0;
 #pragma unroll
-    for (int a = 0; a < C::D; ++a)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) c[a][i] = valid ? R.cand[(size_t)a * R.N + root[i]] : 0ull;
-#pragma unroll
-    for (int a = 0; a < C::D; ++a) {
-        uint32_t* word[4];
-        uint32_t bits[4];
-        bool pend[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            word[i] = nullptr;
-            bits[i] = 0u;
-            pend[i] = false;
-            if ((c[a][i] & 0xFFFFFFFF00000000ull) == tag) {
-                const uint32_t slot = ~(uint32_t)c[a][i];
-                if (slot < nslots) {
-                    const uint32_t crd = (a == 0) ? x + (uint32_t)i : (a == 1) ? y : z;
-                    word[i] = R.bmp + ((size_t)a * nslots + slot) * bw + (crd >> 5);
-                    bits[i] = 1u << (crd & 31u);
-                    pend[i] = true;
-                } else {
-                    flag_error(R, ERR_SLOT);
-                }
-            }
+    for (int k = 0; k < WPL; ++k) {
+        const int w = lane * WPL + k;
+        mw[k] = (w < C::FBW) ? R.fbits[(size_t)t * C::FBW + w] : 0u;
+        if (w < C::FBW) {
+            sm.FBt[w] = mw[k];
+            sm.BF[w] = 0;
         }
-#pragma unroll
-        for (int i = 1; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < i; ++j)
-                if (pend[i] && pend[j] && word[i] == word[j]) {
-                    bits[j] |= bits[i];
-                    pend[i] = false;
-                }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) wave_or(word[i], bits[i], pend[i], wscr);
+        tot += __popc(mw[k]);
     }
+    int inc = tot;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += v;
+    }
+    const int nb = __shfl(inc, 63, 64);
+    int pos = inc - tot;
+#pragma unroll
+    for (int k = 0; k < WPL; ++k) {
+        uint32_t m = mw[k];
+        while (m) {
+            const int b = __ffs(m) - 1;
+            m &= m - 1u;
+            if (pos < CAP) sm.list[pos] = (uint16_t)((lane * WPL + k) * 32 + b);
+            ++pos;
+        }
+    }
+    if (lane == 0) sm.wor = 0;
+    wave_lds_sync();
+    uint64_t rf = 0;   // flip bits of this lane's row
+    {
+        const int ly = lane % C::TY, lz = lane / C::TY;
+        if (ly < g.wy && lz < g.wz)
+            rf = row_flips((uint32_t)g.x0 + (uint32_t)R.L * ((uint32_t)(g.y0 + ly) + (uint32_t)R.L * (uint32_t)(g.z0 + lz)),
+                           g.wx, s, k0, k1);
+    }
+    if (nb > CAP && lane == 0) flag_error(R, ERR_TILE_LABEL);   // more border roots than face sites
+    const int nl = min(nb, CAP);
+    // two list entries per lane and step (i and i + 64), their finds together
+    for (int i = lane; i < nl; i += 128) {
+        const bool two = i + 64 < nl;
+        uint32_t lr[2], gi[2], root[2];
+        lr[0] = sm.list[i];
+        lr[1] = two ? sm.list[i + 64] : lr[0];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) gi[e] = local_to_global<C>(lr[e], g.x0, g.y0, g.z0, R.L);
+        if (gi[0] >= R.N || gi[1] >= R.N) {
+            flag_error(R, ERR_TILE_LABEL);
+            continue;
+        }
+        root[0] = gi[0];
+        root[1] = gi[1];
+        ro_find2(R, root[0], root[1]);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            if (e == 1 && !two) break;
+            if (keep && root[e] != gi[e]) R.par[gi[e]] = (int32_t)root[e];
+            if (flip_bit(root[e], s, k0, k1)) atomicOr(&sm.BF[lr[e] >> 5], 1u << (lr[e] & 31u));
+            sm.root[i + 64 * e] = root[e];
+        }
+    }
+    wave_lds_sync();
+    constexpr int WPR = C::TX / 32;   // bitmap words per row
+#pragma unroll
+    for (int k = 0; k < WPR; ++k) {
+        const int w = lane * WPR + k;
+        const uint32_t fb = sm.FBt[w];
+        R.bflip[(size_t)t * C::FBW + w] = (fb & sm.BF[w]) | (~fb & (uint32_t)(rf >> (32 * k)));
+    }
+    if (pcc) k3a_coverage<C>(R, t, s, g, nl, sm);
 }
+
+// --------------------------------------------------------------------------
+// K3b: cluster flip.  Every site takes the flip bit that K3a recorded for its
+// tile root and gets its cluster's new spin.  Optionally writes the final
+// labels.
+// --------------------------------------------------------------------------
+template <class C>
+struct K3Smem {
+    uint32_t FL[C::FBW];         // flip bit of every tile root (from K3a)
+    uint32_t FBt[C::FBW];        // the tile's border-root bitmap (labels only)
+};
 
 // new spin byte of the site with tile-local index k and stored label v;
-// writes the final label when asked for and returns the cluster root (for
-// the coverage marks)
+// writes the final label when asked for
 template <class C>
 __device__ __forceinline__ uint32_t k3_site(const SwRep& R, const K3Smem<C>& sm, const TileGeo& g, uint32_t v, int k,
-                                            uint32_t gi, bool labels, bool pcc, uint32_t& root_out)
+                                            uint32_t gi, bool labels)
 {
     const uint32_t lr = v;
     if (lr > (uint32_t)k) {                 // a tile root precedes its sites
@@ -1177,7 +1281,7 @@ __device__ __forceinline__ uint32_t k3_site(const SwRep& R, const K3Smem<C>& sm,
         return 0xFFu;
     }
     const uint32_t bit = (sm.FL[lr >> 5] >> (lr & 31u)) & 1u;
-    if (labels || pcc) {
+    if (labels) {
         const bool border = (sm.FBt[lr >> 5] >> (lr & 31u)) & 1u;
         uint32_t root = local_to_global<C>(lr, g.x0, g.y0, g.z0, R.L);
         if (border) root = (uint32_t)R.par[root];   // set to the cluster root by K3a
@@ -1185,13 +1289,12 @@ __device__ __forceinline__ uint32_t k3_site(const SwRep& R, const K3Smem<C>& sm,
             flag_error(R, ERR_PARENT);
             root = 0;
         }
-        if (labels) R.lab32[gi] = (int32_t)root;
-        root_out = root;
+        R.lab32[gi] = (int32_t)root;
     }
     return bit ? 0x01u : 0xFFu;
 }
 
-// K3b when neither final labels nor PCC marks are asked for and rows are
+// K3b when no final labels are asked for and rows are
 // whole groups of W = 4 or 8 sites (the plain sweep): labels in, spins out,
 // one bitmap word per site, W sites per load and store; the label check (a
 // tile root precedes its sites) is folded into one flag per thread
@@ -1251,15 +1354,15 @@ __device__ void k3_lean_tile(const SwRep& R, int t, const TileGeo& g, K3Smem<C>&
 template <class C>
 __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
 {
+    (void)s;
     const int tid = threadIdx.x;
     const TileGeo g = tile_geo<C>(R, t);
     const uint32_t L = (uint32_t)R.L;
     const bool labels = R.lab32 != nullptr;
-    const bool pcc = (R.flags & FLAG_PCC) != 0;
     constexpr int QR = C::TX / 4;                       // quads of sites per row
     constexpr int QPT = C::TS / 4 / kK3Block;           // quads per thread (blockDim = kK3Block)
     const bool quads = (L & 3u) == 0;                   // then every row and the tile width are multiples of 4
-    if (!labels && !pcc && quads) {
+    if (!labels && quads) {
         if ((L & 7u) == 0) k3_lean_tile<C, 8>(R, t, g, sm);
         else k3_lean_tile<C, 4>(R, t, g, sm);
         return;
@@ -1281,19 +1384,13 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
 
     // 1) the tile's flip bitmap (from K3a), and its border bitmap when the
     //    cluster roots are needed
-    if (tid < kK3Block / 64) sm.wor[tid] = 0;
     for (int w = tid; w < C::FBW; w += blockDim.x) {
         sm.FL[w] = R.bflip[(size_t)t * C::FBW + w];
-        if (labels || pcc) sm.FBt[w] = R.fbits[(size_t)t * C::FBW + w];
+        if (labels) sm.FBt[w] = R.fbits[(size_t)t * C::FBW + w];
     }
     __syncthreads();
 
-    // 3) new spins; coverage marks of the PCC candidates (every lane of a
-    //    wave runs the same iterations, for the combined atomics)
-    const uint64_t tag = (uint64_t)(s + 1u) << 32;
-    const uint32_t bw = (L + 31u) / 32u;               // bitmap words per candidate
-    const uint32_t nslots = (C::D == 3) ? L * L : L;   // candidates per axis
-    uint32_t* wscr = &sm.wor[tid >> 6];
+    // 2) new spins (and final labels)
     if (quads) {
 #pragma unroll
         for (int j = 0; j < QPT; ++j) {
@@ -1301,22 +1398,17 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
             const int r = qd / QR, xq = (qd % QR) * 4;
             const int ly = r % C::TY, lz = r / C::TY;
             const bool valid = ly < g.wy && lz < g.wz && xq < g.wx;
+            if (!valid) continue;
             const uint32_t gi = (uint32_t)(g.x0 + xq) + L * ((uint32_t)(g.y0 + ly) + L * (uint32_t)(g.z0 + lz));
             const uint2 v = lv[j];
             const int k = r * C::TX + xq;
             uint32_t out = 0;
-            uint32_t root[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                if (valid) {
-                    const uint32_t vi = (i == 0) ? (v.x & 0xFFFFu) : (i == 1) ? (v.x >> 16) : (i == 2) ? (v.y & 0xFFFFu) : (v.y >> 16);
-                    out |= k3_site<C>(R, sm, g, vi, k + i, gi + (uint32_t)i, labels, pcc, root[i]) << (8 * i);
-                }
+                const uint32_t vi = (i == 0) ? (v.x & 0xFFFFu) : (i == 1) ? (v.x >> 16) : (i == 2) ? (v.y & 0xFFFFu) : (v.y >> 16);
+                out |= k3_site<C>(R, sm, g, vi, k + i, gi + (uint32_t)i, labels) << (8 * i);
             }
-            if (valid) *reinterpret_cast<uint32_t*>(R.spins + gi) = out;
-            if (pcc)
-                pcc_quad<C>(R, root, valid, (uint32_t)(g.x0 + xq), (uint32_t)(g.y0 + ly), (uint32_t)(g.z0 + lz), tag, bw,
-                            nslots, wscr);
+            *reinterpret_cast<uint32_t*>(R.spins + gi) = out;
         }
     } else {
         for (int k0 = 0; k0 < C::TS; k0 += kK3Block) {
@@ -1325,12 +1417,7 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
             const int ly = r % C::TY, lz = r / C::TY;
             const bool valid = ly < g.wy && lz < g.wz && xk < g.wx;
             const uint32_t gi = (uint32_t)(g.x0 + xk) + L * ((uint32_t)(g.y0 + ly) + L * (uint32_t)(g.z0 + lz));
-            uint32_t root = 0;
-            if (valid) R.spins[gi] = (int8_t)k3_site<C>(R, sm, g, R.lab16[gi], k, gi, labels, pcc, root);
-            if (pcc) {
-                const uint32_t crd[3] = {(uint32_t)(g.x0 + xk), (uint32_t)(g.y0 + ly), (uint32_t)(g.z0 + lz)};
-                pcc_mark<C>(R, root, valid, crd, tag, bw, nslots, wscr);
-            }
+            if (valid) R.spins[gi] = (int8_t)k3_site<C>(R, sm, g, R.lab16[gi], k, gi, labels);
         }
     }
     __syncthreads();

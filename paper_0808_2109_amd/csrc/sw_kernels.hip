@@ -1,7 +1,7 @@
 // sw_kernels.hip -- the HIP kernels of the sweep and their host launchers.
 //
-// Plain path: one launch per phase and replica (K1, K2, K3a, K3b, and for PCC
-// the candidate, coverage and feedback kernels), each one workgroup per tile.  Batched path: each
+// Plain path: one launch per phase and replica (K1, K2, [PCC candidates],
+// K3a, K3b, [PCC coverage test and feedback]), each one workgroup per tile.  Batched path: each
 // phase is one launch over the tiles of all replicas, and the launches of
 // many sweeps are replayed from one hipGraph.
 #include "sw_device.hpp"
@@ -88,14 +88,14 @@ __device__ __forceinline__ int xcd_item(int nitems)
 template <class C>
 constexpr int k1_waves() { return C::TX == 64 ? 8 : 6; }
 
-template <class C>
+template <class C, bool PCC>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(k1_waves<C>()))) void k1_kernel(
     const SwRep* Rd, uint32_t s, int64_t* em)
 {
-    __shared__ K1Smem<C> sm;
+    __shared__ K1Smem<C, PCC> sm;
     const SwRep R = *Rd;
     int64_t e = 0, m = 0;
-    k1_tile<C>(R, xcd_item(R.ntiles), s, R.thr, sm, em != nullptr, e, m);
+    k1_tile<C, PCC>(R, xcd_item(R.ntiles), s, R.thr, sm, em != nullptr, e, m);
     if (em) wave_flush_em(e, m, em);
 }
 
@@ -298,11 +298,11 @@ __device__ __forceinline__ void flush_em(int64_t e, int64_t m, int64_t* dst, int
 // The per-item kernels below take either one workgroup per work item (grid =
 // nitems) or a smaller grid whose workgroups each run a contiguous,
 // XCD-aware chunk of the list; the results are the same for any grid.
-template <class C2, class C3>
+template <class C2, class C3, bool PCC>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(k1_waves<C2>()))) void kb1_kernel(
     SwRep* reps, const EngineItem* items, int nitems, int it, int n_sweeps)
 {
-    __shared__ __align__(16) char smem[cmax2(sizeof(K1Smem<C2>), sizeof(K1Smem<C3>))];
+    __shared__ __align__(16) char smem[cmax2(sizeof(K1Smem<C2, PCC>), sizeof(K1Smem<C3, PCC>))];
     int i0, i1;
     chunk_of(nitems, i0, i1);
     for (int i = i0; i < i1; ++i) {
@@ -314,9 +314,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(k1_waves
             dst = R.series + 2 * (size_t)(s - 1 - R.first);
         int64_t e = 0, m = 0;
         if (R.dim == 2)
-            k1_tile<C2>(R, items[i].tile, s, R.thr, *reinterpret_cast<K1Smem<C2>*>(smem), dst != nullptr, e, m);
+            k1_tile<C2, PCC>(R, items[i].tile, s, R.thr, *reinterpret_cast<K1Smem<C2, PCC>*>(smem), dst != nullptr, e,
+                             m);
         else
-            k1_tile<C3>(R, items[i].tile, s, R.thr, *reinterpret_cast<K1Smem<C3>*>(smem), dst != nullptr, e, m);
+            k1_tile<C3, PCC>(R, items[i].tile, s, R.thr, *reinterpret_cast<K1Smem<C3, PCC>*>(smem), dst != nullptr, e,
+                             m);
         if (dst) wave_flush_em(e, m, dst);
     }
 }
@@ -488,11 +490,14 @@ int launch_k1(const SwRep& h, SwRep* d, uint32_t s, int64_t* em, hipStream_t str
     (void)per_cu;
     const int grid = h.ntiles;
     switch (h.dim * 16 + h.shape) {
-#define L1(id, D, X, Y, Z)                                                                  \
-    case (D * 16 + id): {                                                                  \
-        using C = TileCfg<D, X, Y, Z>;                                                     \
-        hipLaunchKernelGGL(k1_kernel<C>, dim3(grid), dim3(K1Cfg<C>::NT), 0, stream, d, s, em); \
-        break;                                                                             \
+#define L1(id, D, X, Y, Z)                                                                            \
+    case (D * 16 + id): {                                                                            \
+        using C = TileCfg<D, X, Y, Z>;                                                               \
+        if (h.flags & FLAG_PCC)                                                                      \
+            hipLaunchKernelGGL((k1_kernel<C, true>), dim3(grid), dim3(K1Cfg<C>::NT), 0, stream, d, s, em); \
+        else                                                                                         \
+            hipLaunchKernelGGL((k1_kernel<C, false>), dim3(grid), dim3(K1Cfg<C>::NT), 0, stream, d, s, em); \
+        break;                                                                                       \
     }
         SW_SHAPES(L1)
         default: return -1;
@@ -604,12 +609,15 @@ int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, i
 #define SW_BATCH(i, C2, C3)                                                                                          \
     case i:                                                                                                          \
         for (int it = 0; it < n_sweeps; ++it) {                                                                      \
-            hipLaunchKernelGGL((kb1_kernel<C2, C3>), dim3(ig), dim3(max(K1Cfg<C2>::NT, K1Cfg<C3>::NT)), 0, stream, reps, items, nitems, it, n_sweeps); \
+            if (any_pcc)                                                                                             \
+                hipLaunchKernelGGL((kb1_kernel<C2, C3, true>), dim3(ig), dim3(max(K1Cfg<C2>::NT, K1Cfg<C3>::NT)), 0, stream, reps, items, nitems, it, n_sweeps); \
+            else                                                                                                     \
+                hipLaunchKernelGGL((kb1_kernel<C2, C3, false>), dim3(ig), dim3(max(K1Cfg<C2>::NT, K1Cfg<C3>::NT)), 0, stream, reps, items, nitems, it, n_sweeps); \
             hipLaunchKernelGGL((kb2_kernel<C2, C3>), dim3(ig), dim3(any_3d ? kBlock : K2Cfg<C2>::NT), 0, stream,     \
                                reps, items, nitems, it, n_sweeps);                                                   \
-            hipLaunchKernelGGL((kb3a_kernel<C2, C3>), dim3(ig), dim3(64), 0, stream, reps, items, nitems, it, n_sweeps); \
             if (any_pcc)                                                                                             \
                 hipLaunchKernelGGL((kbc_kernel<C2, C3>), dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
+            hipLaunchKernelGGL((kb3a_kernel<C2, C3>), dim3(ig), dim3(64), 0, stream, reps, items, nitems, it, n_sweeps); \
             hipLaunchKernelGGL((kb3_kernel<C2, C3>), dim3(ig), dim3(kK3Block), 0, stream, reps, items, nitems, it, n_sweeps); \
             if (any_pcc) {                                                                                           \
                 hipLaunchKernelGGL(kbp_kernel, dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \

@@ -128,11 +128,14 @@ void fill_geometry(SwRep& h, int shape)
     h.ft = shape_ft(h.dim, shape);
 }
 
-// per-tile buffers: crossing bits, border-root bitmaps and their flip bits, face labels
-static uint64_t tile_bytes(const SwRep& h)
+// per-tile buffers: crossing bits, border-root bitmaps and their flip bits,
+// face labels, and for PCC the coverage entries of the border roots
+static uint64_t tile_bytes(const SwRep& h, bool pcc)
 {
     const uint64_t nt = (uint64_t)h.ntiles;
-    return nt * (uint64_t)h.xwords * 4 + 2 * nt * (uint64_t)h.fbw * 4 + nt * 2 * (uint64_t)h.ft * 2;
+    uint64_t b = nt * (uint64_t)h.xwords * 4 + 2 * nt * (uint64_t)h.fbw * 4 + nt * 2 * (uint64_t)h.ft * 2;
+    if (pcc) b += nt * 2 * (uint64_t)h.ft * 16;
+    return b;
 }
 
 uint64_t footprint_bytes(const sw_params* p, int shape)
@@ -143,8 +146,8 @@ uint64_t footprint_bytes(const sw_params* p, int shape)
     h.L = p->L;
     fill_geometry(h, shape);
     uint64_t b = n * (1 + 2 + 4);                            // spins, lab16, par
-    if (p->flags & (SW_KEEP_LABELS | SW_PCC)) b += 4 * n;    // lab32
-    b += tile_bytes(h);                                      // crossing bits, border bitmaps, face labels
+    if (p->flags & SW_KEEP_LABELS) b += 4 * n;               // lab32
+    b += tile_bytes(h, (p->flags & SW_PCC) != 0);            // crossing bits, bitmaps, face labels, coverage
     b += 64;                                                 // accumulators
     if (p->flags & SW_PCC) {
         const uint64_t L = (uint64_t)p->L;
@@ -180,23 +183,27 @@ static void dfree(void* p)
     if (p) (void)hipFree(p);
 }
 
-// the per-tile buffers of a descriptor whose geometry is filled in
+// the per-tile buffers of a descriptor whose geometry and flags are filled in
 static int alloc_tile_buffers(SwRep& h)
 {
     const size_t nt = (size_t)h.ntiles;
     h.xbits = h.fbits = h.bflip = nullptr;
     h.face = nullptr;
+    h.cov = nullptr;
     int rc = dmalloc((void**)&h.xbits, nt * h.xwords * 4, "crossing bits");
     if (!rc) rc = dmalloc((void**)&h.fbits, nt * h.fbw * 4, "border bitmaps");
     if (!rc) rc = dmalloc((void**)&h.bflip, nt * h.fbw * 4, "border flip bits");
     if (!rc) rc = dmalloc((void**)&h.face, nt * 2 * h.ft * 2, "face labels");
+    if (!rc && (h.flags & FLAG_PCC)) rc = dmalloc((void**)&h.cov, nt * 2 * h.ft * 16, "coverage entries");
     if (rc) {
         dfree(h.xbits);
         dfree(h.fbits);
         dfree(h.bflip);
         dfree(h.face);
+        dfree(h.cov);
         h.xbits = h.fbits = h.bflip = nullptr;
         h.face = nullptr;
+        h.cov = nullptr;
     }
     return rc;
 }
@@ -211,6 +218,7 @@ void replica_free(ReplicaH& r)
     dfree(r.h.fbits);
     dfree(r.h.bflip);
     dfree(r.h.face);
+    dfree(r.h.cov);
     dfree(r.h.series);
     dfree(r.h.acc);
     dfree(r.h.cand);
@@ -225,6 +233,7 @@ void replica_free(ReplicaH& r)
     r.h.face = nullptr;
     r.h.series = r.h.acc = nullptr;
     r.h.cand = nullptr;
+    r.h.cov = nullptr;
     r.h.p_trace = nullptr;
 }
 
@@ -256,7 +265,7 @@ int replica_alloc(ReplicaH& r, const sw_params* p, int shape, hipStream_t stream
     if ((rc = dmalloc((void**)&h.spins, n, "spins"))) goto bad;
     if ((rc = dmalloc((void**)&h.lab16, 2 * n, "tile labels"))) goto bad;
     if ((rc = dmalloc((void**)&h.par, 4 * n, "union-find parents"))) goto bad;
-    if (h.flags & (FLAG_KEEP | FLAG_PCC))
+    if (h.flags & FLAG_KEEP)
         if ((rc = dmalloc((void**)&h.lab32, 4 * n, "labels"))) goto bad;
     if ((rc = alloc_tile_buffers(h))) goto bad;
     if ((rc = dmalloc((void**)&h.acc, 64, "accumulators"))) goto bad;
@@ -495,8 +504,8 @@ int plain_sweep(sw_lattice* h, int r, int32_t n)
         }
         TIMED(h, 0, launch_k1(m, d, s, em, h->stream, h->per_cu[0]));
         TIMED(h, 1, launch_k2(m, d, h->stream));
-        TIMED(h, 6, launch_k3a(m, d, s, h->stream));
         if (pcc) TIMED(h, 3, launch_cand(m, d, s, h->stream));
+        TIMED(h, 6, launch_k3a(m, d, s, h->stream));
         TIMED(h, 2, launch_k3(m, d, s, h->stream, h->per_cu[2]));
         if (pcc) TIMED(h, 3, launch_perc(m, d, s, h->stream));
     }
@@ -837,7 +846,7 @@ int sw_get_labels(sw_lattice* h, int32_t replica, int32_t* host_buf, int64_t cap
     int rc = check_rep(h, replica);
     if (rc) return rc;
     SwRep& m = h->reps[replica].h;
-    if (!m.lab32) return fail(SW_ESTATE, "labels are kept only with SW_KEEP_LABELS or SW_PCC");
+    if (!m.lab32) return fail(SW_ESTATE, "labels are kept only with SW_KEEP_LABELS");
     if (!h->reps[replica].labels_valid) return fail(SW_ESTATE, "no sweep done yet");
     if (!host_buf || cap < (int64_t)m.N) return fail(SW_EINVAL, "buffer smaller than N");
     rc = set_device(h);
@@ -991,6 +1000,7 @@ int sw_set_tile_shape(sw_lattice* h, int32_t replica, int32_t shape)
     dfree(r.h.fbits);
     dfree(r.h.bflip);
     dfree(r.h.face);
+    dfree(r.h.cov);
     r.h = probe;
     h->items_dirty = true;
     return push_desc(h, replica);
