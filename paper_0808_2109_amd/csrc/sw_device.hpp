@@ -1119,60 +1119,78 @@ struct K3aSmem {
 // its tile cluster occupies (K1's coverage entry, shifted to the tile's
 // origin) into the slot's bitmap.  Marks of one bitmap word are combined over
 // the wave before the global atomic; every lane runs the same iterations.
-template <class C>
-__device__ void k3a_coverage(const SwRep& R, int t, uint32_t s, const TileGeo& g, int nl, K3aSmem<C>& sm)
+// (The axis loop stays rolled, and the callers make one call after the tile's
+// K3a with the dimension as data: unrolled, or inlined once per dimension in
+// the batched kernel, its wave-combining loops triple the register count of
+// every K3a.)
+struct CovArgs {
+    int32_t dim, ty;                 // dimension and tile extent in y (bits of y in the row word)
+    uint32_t L, N, s;
+    int32_t x0, y0, z0, wx, wy, wz;
+    const uint64_t* cand;
+    uint32_t* bmp;
+    const unsigned long long* cov;   // the tile's coverage entries
+    int32_t* err;
+    int nl;                          // border roots of the tile
+    const uint32_t* roots;           // their cluster roots (LDS)
+    uint32_t* wscr;                  // LDS word for combining marks over the wave
+};
+
+static __device__ __forceinline__ void k3a_coverage(const CovArgs& A)
 {
-    constexpr int CAP = 2 * C::FT;
     const int lane = threadIdx.x & 63;
-    const uint64_t tag = (uint64_t)(s + 1u) << 32;
-    const uint32_t L = (uint32_t)R.L;
-    const uint32_t bw = (L + 31u) / 32u;
-    const uint32_t nslots = (C::D == 3) ? L * L : L;
-    const unsigned long long* cov = reinterpret_cast<const unsigned long long*>(R.cov) + (size_t)t * (2 * CAP);
+    const int nl = A.nl;
+    const uint64_t tag = (uint64_t)(A.s + 1u) << 32;
+    const uint32_t bw = (A.L + 31u) / 32u;
+    const uint32_t nslots = (A.dim == 3) ? A.L * A.L : A.L;
     wave_lds_sync();
     for (int base = 0; base < nl; base += 64) {
         const int k = base + lane;
         const bool valid = k < nl;
-        const uint32_t root = valid ? sm.root[k] : 0u;
-        const unsigned long long ca = valid ? cov[2 * k] : 0ull, cb = valid ? cov[2 * k + 1] : 0ull;
-#pragma unroll
-        for (int a = 0; a < C::D; ++a) {
+        const uint32_t root = valid ? A.roots[k] : 0u;
+        const unsigned long long ca = valid ? A.cov[2 * k] : 0ull, cb = valid ? A.cov[2 * k + 1] : 0ull;
+#pragma unroll 1
+        for (int a = 0; a < A.dim; ++a) {
             bool cand = false;
             uint32_t slot = 0;
-            if (valid && root < R.N) {
-                const uint64_t c = R.cand[(size_t)a * R.N + root];
+            if (valid && root < A.N) {
+                const uint64_t c = A.cand[(size_t)a * A.N + root];
                 if ((c & 0xFFFFFFFF00000000ull) == tag) {
                     slot = ~(uint32_t)c;
                     if (slot < nslots) cand = true;
-                    else flag_error(R, ERR_SLOT);
+                    else if (A.err) atomicOr(A.err, 1 << ERR_SLOT);
                 }
             }
-            // this cluster's axis-a coordinates in the tile, from the tile's origin on
+            // this cluster's axis-a coordinates in the tile, from the tile's
+            // origin on (masked to the tile's extent, so that no mark can
+            // leave the bitmap)
             uint64_t bits;
             uint32_t c0;
             if (a == 0) {
-                bits = ca & low_bits(C::TX);
-                c0 = (uint32_t)g.x0;
+                bits = ca & low_bits(A.wx);
+                c0 = (uint32_t)A.x0;
             } else if (a == 1) {
-                bits = cb & low_bits(C::TY);
-                c0 = (uint32_t)g.y0;
+                bits = cb & low_bits(A.wy);
+                c0 = (uint32_t)A.y0;
             } else {
-                bits = (cb >> C::TY) & low_bits(C::TZ);
-                c0 = (uint32_t)g.z0;
+                bits = (cb >> A.ty) & low_bits(A.wz);
+                c0 = (uint32_t)A.z0;
             }
             // tile origins are multiples of the extent (32 / 64 in x, 64 in 2D y,
             // 8 in 3D y and z), so the shifted bits stay within two words
             const uint64_t sb = bits << (c0 & 31u);
-            uint32_t* row = R.bmp + ((size_t)a * nslots + slot) * bw + (c0 >> 5);
+            uint32_t* row = A.bmp + ((size_t)a * nslots + slot) * bw + (c0 >> 5);
             const uint32_t lo = (uint32_t)sb, hi = (uint32_t)(sb >> 32);
-            wave_or(row, lo, cand && lo != 0u, &sm.wor);
-            wave_or(row + 1, hi, cand && hi != 0u, &sm.wor);
+            wave_or(row, lo, cand && lo != 0u, A.wscr);
+            wave_or(row + 1, hi, cand && hi != 0u, A.wscr);
         }
     }
 }
 
+// Returns, for PCC replicas, the arguments of the coverage marks (cov.nl < 0:
+// none to make); the caller runs k3a_coverage after it.
 template <class C>
-__device__ void k3a_tile(const SwRep& R, int t, uint32_t s, K3aSmem<C>& sm)
+__device__ void k3a_tile(const SwRep& R, int t, uint32_t s, K3aSmem<C>& sm, CovArgs& cov)
 {
     constexpr int CAP = 2 * C::FT;
     const int lane = threadIdx.x & 63;
@@ -1255,7 +1273,11 @@ __device__ void k3a_tile(const SwRep& R, int t, uint32_t s, K3aSmem<C>& sm)
         const uint32_t fb = sm.FBt[w];
         R.bflip[(size_t)t * C::FBW + w] = (fb & sm.BF[w]) | (~fb & (uint32_t)(rf >> (32 * k)));
     }
-    if (pcc) k3a_coverage<C>(R, t, s, g, nl, sm);
+    cov.nl = -1;
+    if (pcc)
+        cov = CovArgs{C::D, C::TY, (uint32_t)R.L, R.N, s, g.x0, g.y0, g.z0, g.wx, g.wy, g.wz, R.cand, R.bmp,
+                      reinterpret_cast<const unsigned long long*>(R.cov) + (size_t)t * (2 * CAP), R.err, nl, sm.root,
+                      &sm.wor};
 }
 
 // --------------------------------------------------------------------------

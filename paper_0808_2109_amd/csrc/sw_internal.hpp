@@ -14,6 +14,8 @@ struct EngineItem {
     int32_t tile;
 };
 
+constexpr int kPercChunk = 64;   // candidate slots per workgroup of the batched coverage test
+
 int device_cu_count();
 uint64_t device_wallclock_hz();
 
@@ -29,10 +31,14 @@ int launch_set_state(SwRep* d, uint32_t sweep, uint32_t measured, uint32_t first
                      hipStream_t stream);
 // enqueue n sweeps of every active replica as batched phase launches (used
 // under stream capture to build the batch graph)
-// (grid: workgroups of the list-chunking kernels; item_grid: workgroups of the
+// (any_pcc: bit 0 a 2D PCC replica is active, bit 1 a 3D one; grid:
+// workgroups of the list-chunking kernels; item_grid: workgroups of the
 // per-tile phase kernels, nitems for one workgroup per work item)
-int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, int nitems, int n_sweeps, int any_pcc,
-                 int any_series, int any_3d, int grid, int item_grid, hipStream_t stream);
+// cand_items: the tiles of PCC replicas on a hyperplane x_a = 0; perc_items:
+// (replica, k) for the candidate slots [k * kPercChunk, (k + 1) * kPercChunk)
+int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, int nitems, const EngineItem* cand_items,
+                 int ncand, const EngineItem* perc_items, int nperc, int n_sweeps, int any_pcc, int any_series,
+                 int any_3d, int grid, int item_grid, hipStream_t stream);
 
 int shape_count(int dim);
 int shape_extents(int dim, int id, int* tx, int* ty, int* tz);

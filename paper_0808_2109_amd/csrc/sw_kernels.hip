@@ -113,7 +113,9 @@ __global__ __launch_bounds__(64) void k3a_kernel(const SwRep* Rd, uint32_t s)
 {
     __shared__ K3aSmem<C> sm;
     const SwRep R = *Rd;
-    k3a_tile<C>(R, xcd_item(R.ntiles), s, sm);
+    CovArgs cov;
+    k3a_tile<C>(R, xcd_item(R.ntiles), s, sm, cov);
+    if (cov.nl >= 0) k3a_coverage(cov);
 }
 
 // K3b: one workgroup per tile, grid = ntiles (XCD-aware order)
@@ -296,15 +298,31 @@ __device__ __forceinline__ void flush_em(int64_t e, int64_t m, int64_t* dst, int
 // threads as the larger of the two tiles needs), with E, M of the incoming
 // configuration added to the replica's series entry
 // The per-item kernels below take either one workgroup per work item (grid =
-// nitems) or a smaller grid whose workgroups each run a contiguous,
-// XCD-aware chunk of the list; the results are the same for any grid.
-template <class C2, class C3, bool PCC>
+// nitems, LOOP = false) or a smaller grid whose workgroups each run a
+// contiguous, XCD-aware chunk of the list (LOOP = true); the results are the
+// same for any grid.  The two are separate instantiations: with the item loop
+// the compiler keeps far more registers live in the tile labelling.
+template <bool LOOP>
+__device__ __forceinline__ void item_range(int nitems, int& i0, int& i1)
+{
+    if (LOOP) {
+        chunk_of(nitems, i0, i1);
+    } else {
+        i0 = xcd_item(nitems);
+        i1 = i0 + 1;
+    }
+}
+
+// (P2, P3: the PCC instantiation of the 2D / 3D tile labelling, chosen when
+// a 2D / 3D PCC replica is active, so that the shared memory is sized for
+// what the batch needs)
+template <class C2, class C3, bool P2, bool P3, bool LOOP>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(k1_waves<C2>()))) void kb1_kernel(
     SwRep* reps, const EngineItem* items, int nitems, int it, int n_sweeps)
 {
-    __shared__ __align__(16) char smem[cmax2(sizeof(K1Smem<C2, PCC>), sizeof(K1Smem<C3, PCC>))];
+    __shared__ __align__(16) char smem[cmax2(sizeof(K1Smem<C2, P2>), sizeof(K1Smem<C3, P3>))];
     int i0, i1;
-    chunk_of(nitems, i0, i1);
+    item_range<LOOP>(nitems, i0, i1);
     for (int i = i0; i < i1; ++i) {
         const SwRep& R = reps[items[i].rep];
         uint32_t s;
@@ -314,23 +332,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(k1_waves
             dst = R.series + 2 * (size_t)(s - 1 - R.first);
         int64_t e = 0, m = 0;
         if (R.dim == 2)
-            k1_tile<C2, PCC>(R, items[i].tile, s, R.thr, *reinterpret_cast<K1Smem<C2, PCC>*>(smem), dst != nullptr, e,
-                             m);
+            k1_tile<C2, P2>(R, items[i].tile, s, R.thr, *reinterpret_cast<K1Smem<C2, P2>*>(smem), dst != nullptr, e, m);
         else
-            k1_tile<C3, PCC>(R, items[i].tile, s, R.thr, *reinterpret_cast<K1Smem<C3, PCC>*>(smem), dst != nullptr, e,
-                             m);
+            k1_tile<C3, P3>(R, items[i].tile, s, R.thr, *reinterpret_cast<K1Smem<C3, P3>*>(smem), dst != nullptr, e, m);
         if (dst) wave_flush_em(e, m, dst);
     }
 }
 
 // K2 over the work list
-template <class C2, class C3>
+template <class C2, class C3, bool LOOP>
 __global__ __launch_bounds__(kBlock) void kb2_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
                                                      int n_sweeps)
 {
     __shared__ __align__(16) char smem[cmax2(sizeof(K2Smem<C2>), sizeof(K2Smem<C3>))];
     int i0, i1;
-    chunk_of(nitems, i0, i1);
+    item_range<LOOP>(nitems, i0, i1);
     for (int i = i0; i < i1; ++i) {
         const SwRep& R = reps[items[i].rep];
         uint32_t s;
@@ -340,45 +356,47 @@ __global__ __launch_bounds__(kBlock) void kb2_kernel(SwRep* reps, const EngineIt
     }
 }
 
+// PCC candidates: one workgroup per item of the candidate list, which holds
+// the tiles of PCC replicas that lie on a hyperplane x_a = 0
 template <class C2, class C3>
 __global__ __launch_bounds__(kBlock) void kbc_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
                                                      int n_sweeps)
 {
-    int i0, i1;
-    chunk_of(nitems, i0, i1);
-    for (int i = i0; i < i1; ++i) {
-        const SwRep& R = reps[items[i].rep];
-        uint32_t s;
-        if (!(R.flags & FLAG_PCC) || !rep_runs(R, it, n_sweeps, s)) continue;
-        if (R.dim == 2) k_cand_tile<C2>(R, items[i].tile, s);
-        else k_cand_tile<C3>(R, items[i].tile, s);
-    }
+    const int i = (int)blockIdx.x;
+    if (i >= nitems) return;
+    const SwRep R = reps[items[i].rep];
+    uint32_t s;
+    if (!(R.flags & FLAG_PCC) || !rep_runs(R, it, n_sweeps, s)) return;
+    if (R.dim == 2) k_cand_tile<C2>(R, items[i].tile, s);
+    else k_cand_tile<C3>(R, items[i].tile, s);
 }
 
-template <class C2, class C3>
+template <class C2, class C3, bool LOOP>
 __global__ __launch_bounds__(64) void kb3a_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
                                                   int n_sweeps)
 {
     __shared__ __align__(16) char smem[cmax2(sizeof(K3aSmem<C2>), sizeof(K3aSmem<C3>))];
     int i0, i1;
-    chunk_of(nitems, i0, i1);
+    item_range<LOOP>(nitems, i0, i1);
     for (int i = i0; i < i1; ++i) {
         const SwRep& R = reps[items[i].rep];
         uint32_t s;
         if (!rep_runs(R, it, n_sweeps, s)) continue;
         wave_lds_sync();   // the previous item's reads of the tables are done
-        if (R.dim == 2) k3a_tile<C2>(R, items[i].tile, s, *reinterpret_cast<K3aSmem<C2>*>(smem));
-        else k3a_tile<C3>(R, items[i].tile, s, *reinterpret_cast<K3aSmem<C3>*>(smem));
+        CovArgs cov;
+        if (R.dim == 2) k3a_tile<C2>(R, items[i].tile, s, *reinterpret_cast<K3aSmem<C2>*>(smem), cov);
+        else k3a_tile<C3>(R, items[i].tile, s, *reinterpret_cast<K3aSmem<C3>*>(smem), cov);
+        if (cov.nl >= 0) k3a_coverage(cov);
     }
 }
 
-template <class C2, class C3>
+template <class C2, class C3, bool LOOP>
 __global__ __launch_bounds__(kK3Block) void kb3_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
                                                      int n_sweeps)
 {
     __shared__ __align__(16) char smem[cmax2(sizeof(K3Smem<C2>), sizeof(K3Smem<C3>))];
     int i0, i1;
-    chunk_of(nitems, i0, i1);
+    item_range<LOOP>(nitems, i0, i1);
     for (int i = i0; i < i1; ++i) {
         const SwRep& R = reps[items[i].rep];
         uint32_t s;
@@ -388,27 +406,26 @@ __global__ __launch_bounds__(kK3Block) void kb3_kernel(SwRep* reps, const Engine
     }
 }
 
-// PCC coverage test: tile t of a replica checks its share of the candidate slots
+// PCC coverage test: one workgroup per item of the slot list, whose item
+// (replica, k) stands for the candidate slots [k * kPercChunk, (k + 1) *
+// kPercChunk) of every axis of that replica
 __global__ __launch_bounds__(kBlock) void kbp_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
                                                      int n_sweeps)
 {
     __shared__ int pflag_local;
-    int i0, i1;
-    chunk_of(nitems, i0, i1);
-    for (int i = i0; i < i1; ++i) {
-        const SwRep& R = reps[items[i].rep];
-        uint32_t s;
-        if (!(R.flags & FLAG_PCC) || !rep_runs(R, it, n_sweeps, s)) continue;
-        const uint32_t nslots = (R.dim == 3) ? (uint32_t)R.L * (uint32_t)R.L : (uint32_t)R.L;
-        const int t = items[i].tile;
-        const uint32_t c0 = (uint32_t)(((uint64_t)t * nslots) / (uint32_t)R.ntiles);
-        const uint32_t c1 = (uint32_t)(((uint64_t)(t + 1) * nslots) / (uint32_t)R.ntiles);
-        if (threadIdx.x == 0) pflag_local = 0;
-        __syncthreads();
-        perc_chunk(R, c0, c1, &pflag_local);
-        __syncthreads();
-        if (threadIdx.x == 0 && pflag_local) atomicOr(R.pflag, 1);
-    }
+    const int i = (int)blockIdx.x;
+    if (i >= nitems) return;
+    const SwRep R = reps[items[i].rep];
+    uint32_t s;
+    if (!(R.flags & FLAG_PCC) || !rep_runs(R, it, n_sweeps, s)) return;
+    const uint32_t nslots = (R.dim == 3) ? (uint32_t)R.L * (uint32_t)R.L : (uint32_t)R.L;
+    const uint32_t c0 = min(nslots, (uint32_t)items[i].tile * (uint32_t)kPercChunk);
+    const uint32_t c1 = min(nslots, c0 + (uint32_t)kPercChunk);
+    if (threadIdx.x == 0) pflag_local = 0;
+    __syncthreads();
+    perc_chunk(R, c0, c1, &pflag_local);
+    __syncthreads();
+    if (threadIdx.x == 0 && pflag_local) atomicOr(R.pflag, 1);
 }
 
 // PCC feedback: one thread per replica
@@ -556,7 +573,7 @@ int launch_k3(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream, int per_
 
 int launch_cand(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream)
 {
-    const int grid = grid_for(h.ntiles, 4);
+    const int grid = h.ntiles;   // one tile per workgroup: only the tiles on x_a = 0 planes work
     switch (h.dim * 16 + h.shape) {
 #define LC(id, D, X, Y, Z) SW_LAUNCH_CASE(id, D, X, Y, Z, kcand_kernel, d, s)
         SW_SHAPES(LC)
@@ -600,27 +617,40 @@ int launch_set_state(SwRep* d, uint32_t sweep, uint32_t measured, uint32_t first
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, int nitems, int n_sweeps, int any_pcc,
-                 int any_series, int any_3d, int grid, int item_grid, hipStream_t stream)
+int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, int nitems, const EngineItem* cand_items,
+                 int ncand, const EngineItem* perc_items, int nperc, int n_sweeps, int any_pcc, int any_series,
+                 int any_3d, int grid, int item_grid, hipStream_t stream)
 {
     const int rgrid = (nreps + kBlock - 1) / kBlock;
+    const bool pcc2 = (any_pcc & 1) != 0, pcc3 = (any_pcc & 2) != 0;   // a 2D / 3D PCC replica is active
+    const bool loop = item_grid < nitems;                                // workgroups take chunks of the list
     const int ig = item_grid;
     switch (variant) {
+#define SW_PHASES(C2, C3, LP)                                                                                        \
+    {                                                                                                                \
+        const dim3 b1(max(K1Cfg<C2>::NT, K1Cfg<C3>::NT));                                                            \
+        if (pcc2 && pcc3)                                                                                            \
+            hipLaunchKernelGGL((kb1_kernel<C2, C3, true, true, LP>), dim3(ig), b1, 0, stream, reps, items, nitems, it, n_sweeps); \
+        else if (pcc2)                                                                                               \
+            hipLaunchKernelGGL((kb1_kernel<C2, C3, true, false, LP>), dim3(ig), b1, 0, stream, reps, items, nitems, it, n_sweeps); \
+        else if (pcc3)                                                                                               \
+            hipLaunchKernelGGL((kb1_kernel<C2, C3, false, true, LP>), dim3(ig), b1, 0, stream, reps, items, nitems, it, n_sweeps); \
+        else                                                                                                         \
+            hipLaunchKernelGGL((kb1_kernel<C2, C3, false, false, LP>), dim3(ig), b1, 0, stream, reps, items, nitems, it, n_sweeps); \
+        hipLaunchKernelGGL((kb2_kernel<C2, C3, LP>), dim3(ig), dim3(any_3d ? kBlock : K2Cfg<C2>::NT), 0, stream, reps,    \
+                           items, nitems, it, n_sweeps);                                                             \
+        if (any_pcc && ncand > 0)                                                                                    \
+            hipLaunchKernelGGL((kbc_kernel<C2, C3>), dim3(ncand), dim3(kBlock), 0, stream, reps, cand_items, ncand, it, n_sweeps); \
+        hipLaunchKernelGGL((kb3a_kernel<C2, C3, LP>), dim3(ig), dim3(64), 0, stream, reps, items, nitems, it, n_sweeps); \
+        hipLaunchKernelGGL((kb3_kernel<C2, C3, LP>), dim3(ig), dim3(kK3Block), 0, stream, reps, items, nitems, it, n_sweeps); \
+    }
 #define SW_BATCH(i, C2, C3)                                                                                          \
     case i:                                                                                                          \
         for (int it = 0; it < n_sweeps; ++it) {                                                                      \
-            if (any_pcc)                                                                                             \
-                hipLaunchKernelGGL((kb1_kernel<C2, C3, true>), dim3(ig), dim3(max(K1Cfg<C2>::NT, K1Cfg<C3>::NT)), 0, stream, reps, items, nitems, it, n_sweeps); \
-            else                                                                                                     \
-                hipLaunchKernelGGL((kb1_kernel<C2, C3, false>), dim3(ig), dim3(max(K1Cfg<C2>::NT, K1Cfg<C3>::NT)), 0, stream, reps, items, nitems, it, n_sweeps); \
-            hipLaunchKernelGGL((kb2_kernel<C2, C3>), dim3(ig), dim3(any_3d ? kBlock : K2Cfg<C2>::NT), 0, stream,     \
-                               reps, items, nitems, it, n_sweeps);                                                   \
-            if (any_pcc)                                                                                             \
-                hipLaunchKernelGGL((kbc_kernel<C2, C3>), dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
-            hipLaunchKernelGGL((kb3a_kernel<C2, C3>), dim3(ig), dim3(64), 0, stream, reps, items, nitems, it, n_sweeps); \
-            hipLaunchKernelGGL((kb3_kernel<C2, C3>), dim3(ig), dim3(kK3Block), 0, stream, reps, items, nitems, it, n_sweeps); \
+            if (loop) SW_PHASES(C2, C3, true) else SW_PHASES(C2, C3, false)                                          \
             if (any_pcc) {                                                                                           \
-                hipLaunchKernelGGL(kbp_kernel, dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
+                if (nperc > 0)                                                                                       \
+                    hipLaunchKernelGGL(kbp_kernel, dim3(nperc), dim3(kBlock), 0, stream, reps, perc_items, nperc, it, n_sweeps); \
                 hipLaunchKernelGGL(kbu_kernel, dim3(rgrid), dim3(kBlock), 0, stream, reps, nreps, it, n_sweeps);     \
             }                                                                                                        \
         }                                                                                                            \

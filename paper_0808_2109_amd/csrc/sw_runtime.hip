@@ -527,11 +527,26 @@ int plain_sweep(sw_lattice* h, int r, int32_t n)
 
 static int build_items(sw_lattice* h)
 {
-    std::vector<EngineItem> items;
+    std::vector<EngineItem> items, cand, perc;
     for (size_t r = 0; r < h->reps.size(); ++r) {
-        if (!h->reps[r].h.active) continue;
-        for (int t = 0; t < h->reps[r].h.ntiles; ++t) items.push_back(EngineItem{(int32_t)r, t});
+        const SwRep& m = h->reps[r].h;
+        if (!m.active) continue;
+        for (int t = 0; t < m.ntiles; ++t) {
+            items.push_back(EngineItem{(int32_t)r, t});
+            const int ix = t % m.ntx, iy = (t / m.ntx) % m.nty, iz = t / (m.ntx * m.nty);
+            if ((m.flags & FLAG_PCC) && (ix == 0 || iy == 0 || (m.dim == 3 && iz == 0)))
+                cand.push_back(EngineItem{(int32_t)r, t});
+        }
+        if (m.flags & FLAG_PCC) {
+            const int64_t nslots = (m.dim == 3) ? (int64_t)m.L * m.L : (int64_t)m.L;
+            for (int64_t k = 0; k * kPercChunk < nslots; ++k) perc.push_back(EngineItem{(int32_t)r, (int32_t)k});
+        }
     }
+    const size_t nlist = items.size();
+    h->ncand = (int)cand.size();
+    h->nperc = (int)perc.size();
+    items.insert(items.end(), cand.begin(), cand.end());
+    items.insert(items.end(), perc.begin(), perc.end());
     if (h->items_cap < items.size()) {
         dfree(h->items);
         h->items = nullptr;
@@ -544,7 +559,7 @@ static int build_items(sw_lattice* h)
         hipError_t e = hipMemcpy(h->items, items.data(), items.size() * sizeof(EngineItem), hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "uploading the engine work list");
     }
-    h->nitems = (int)items.size();
+    h->nitems = (int)nlist;
     h->items_dirty = false;
     h->graph_n = -1;    // work list changed: re-capture
     return SW_OK;
@@ -586,13 +601,14 @@ int batched_sweep(sw_lattice* h, int32_t n)
             return fail(SW_EHIP, "state update launch failed");
         rep.dev_count_stale = false;
     }
-    bool any_pcc = false, any_series = false, any_3d = false;
+    int pcc_dims = 0;   // bit 0: a 2D PCC replica is active, bit 1: a 3D one
+    bool any_series = false, any_3d = false;
     for (size_t r = 0; r < h->reps.size(); ++r) {
         SwRep& m = h->reps[r].h;
         if (!m.active) continue;
         rc = ensure_capacity(h, (int)r, std::min<uint64_t>((uint64_t)m.sweep + (uint64_t)n, (uint64_t)m.limit));
         if (rc) return rc;
-        any_pcc = any_pcc || (m.flags & FLAG_PCC);
+        if (m.flags & FLAG_PCC) pcc_dims |= (m.dim == 2) ? 1 : 2;
         any_series = any_series || (m.flags & FLAG_SERIES);
         any_3d = any_3d || m.dim == 3;
     }
@@ -616,12 +632,13 @@ int batched_sweep(sw_lattice* h, int32_t n)
     const int grid = clamp_grid(device_cu_count() * (per_cu > 0 ? per_cu : 8));
     const int item_grid = per_cu > 0 ? clamp_grid(device_cu_count() * per_cu) : h->nitems;
     if (h->graph_n != n || h->graph_grid != grid || h->graph_item_grid != item_grid ||
-        h->graph_flags != (int)(any_3d * 4 + any_pcc * 2 + any_series) || h->graph_variant != variant) {
+        h->graph_flags != (int)(any_3d * 8 + pcc_dims * 2 + any_series) || h->graph_variant != variant) {
         drop_graph(h);
         hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-        int lrc = launch_batch(variant, h->d_reps, (int)h->reps.size(), h->items, h->nitems, n, any_pcc, any_series,
-                               any_3d, grid, item_grid, h->stream);
+        int lrc = launch_batch(variant, h->d_reps, (int)h->reps.size(), h->items, h->nitems, h->items + h->nitems,
+                               h->ncand, h->items + h->nitems + h->ncand, h->nperc, n, pcc_dims, any_series, any_3d,
+                               grid, item_grid, h->stream);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(h->stream, &g);
         if (lrc || e != hipSuccess || !g) {
@@ -637,7 +654,7 @@ int batched_sweep(sw_lattice* h, int32_t n)
         h->graph_n = n;
         h->graph_grid = grid;
         h->graph_item_grid = item_grid;
-        h->graph_flags = (int)(any_3d * 4 + any_pcc * 2 + any_series);
+        h->graph_flags = (int)(any_3d * 8 + pcc_dims * 2 + any_series);
         h->graph_variant = variant;
     }
     hipEvent_t ev;

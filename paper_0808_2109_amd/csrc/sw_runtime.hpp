@@ -58,9 +58,11 @@ struct sw_lattice {
     double ms[sw::kPhases] = {};
     int64_t launches[sw::kPhases] = {};
     // batched execution (work list of all replicas' tiles, replayed graph)
-    sw::EngineItem* items = nullptr;
+    sw::EngineItem* items = nullptr;    // the work list, then the PCC candidate and slot lists
     size_t items_cap = 0;
     int nitems = 0;
+    int ncand = 0;                       // PCC tiles on a hyperplane x_a = 0 (after the work list)
+    int nperc = 0;                       // PCC slot chunks (after the candidate list)
     bool items_dirty = true;
     int batch_per_cu = 0;               // workgroups per CU of the batched phase launches (0: one per tile)
     hipGraph_t graph = nullptr;
