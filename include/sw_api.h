@@ -66,7 +66,12 @@ enum {
 enum {
     SW_RECORD_SERIES = 1u << 0, /* record (E_int, M) after every sweep          */
     SW_KEEP_LABELS = 1u << 1,   /* keep the int32 labels of the last sweep       */
-    SW_PCC = 1u << 2            /* probability-changing-cluster feedback (Sec. III) */
+    SW_PCC = 1u << 2,           /* probability-changing-cluster feedback (Sec. III) */
+    SW_BITPACK = 1u << 3        /* keep the spins (the +-1 of Sec. I) as one bit per
+                                   site on the device: ceil(N/32) uint32 words, site
+                                   i up iff bit i%32 of word i/32 is set.  Every
+                                   result is the same as with int8 spins; sw_get_spins
+                                   and sw_set_spins still take int8 arrays. */
 };
 
 /* execution modes of a multi-replica handle (sw_set_mode) */
@@ -84,7 +89,7 @@ enum {
  *   p_bond          < 0: P = 1 - exp(-2J/T) (evaluated as -expm1(-2J/T) in double);
  *                   in [0,1]: use this P directly (the PCC start value)
  *   seed            key of the random stream
- *   flags           SW_RECORD_SERIES | SW_KEEP_LABELS | SW_PCC
+ *   flags           SW_RECORD_SERIES | SW_KEEP_LABELS | SW_PCC | SW_BITPACK
  *   pcc_dp0         PCC step dp at sweep 0 (> 0)
  *   pcc_halve_every dp is halved every this many sweeps (> 0)
  *   series_cap      capacity of the (E_int, M) series in sweeps (0: grows on demand)
@@ -157,7 +162,8 @@ int sw_measure(sw_lattice* h, int32_t replica, int64_t* e_int, int64_t* m);
 int sw_get_series(sw_lattice* h, int32_t replica, int64_t* host_buf, int64_t cap, int64_t* count,
                   int64_t* first_sweep);
 
-/* Copy the N spins of a replica to host memory (cap >= N).  Synchronises. */
+/* Copy the N spins of a replica to host memory as int8 +1/-1 (cap >= N; a
+ * bit-packed replica is unpacked on the host).  Synchronises. */
 int sw_get_spins(sw_lattice* h, int32_t replica, int8_t* host_buf, int64_t cap);
 
 /* Copy the N canonical labels of the last sweep (needs SW_KEEP_LABELS and at
@@ -185,9 +191,10 @@ int sw_get_pcc_trace(sw_lattice* h, int32_t replica, int32_t* perc, double* p, i
 int sw_set_spins(sw_lattice* h, int32_t replica, const int8_t* host_buf, int64_t n, uint32_t sweep,
                  double p);
 
-/* Use a caller-owned device buffer of N int8 as the replica's spin array (its
- * contents become the current configuration).  The library never frees it;
- * it must stay valid until sw_free or the next bind. */
+/* Use a caller-owned device buffer as the replica's spin array (its contents
+ * become the current configuration): N int8 of +1/-1, or for a SW_BITPACK
+ * replica ceil(N/32) uint32 words in the packed layout.  The library never
+ * frees it; it must stay valid until sw_free or the next bind. */
 int sw_bind_device_spins(sw_lattice* h, int32_t replica, void* dev_ptr);
 
 /* Enable per-phase kernel timing with HIP events on the handle's stream. */

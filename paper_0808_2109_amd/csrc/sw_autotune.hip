@@ -87,7 +87,7 @@ static int copy_state(sw_lattice* s, int r, const sw_lattice* h, int src)
 {
     const SwRep& from = h->reps[src].h;
     SwRep& to = s->reps[r].h;
-    hipError_t e = hipMemcpyAsync(to.spins, from.spins, from.N, hipMemcpyDeviceToDevice, s->stream);
+    hipError_t e = hipMemcpyAsync(to.spins, from.spins, spin_bytes(from), hipMemcpyDeviceToDevice, s->stream);
     if (e != hipSuccess) return hip_fail(e, "copying spins to the tuning lattice");
     to.sweep = from.sweep;
     to.thr = from.thr;

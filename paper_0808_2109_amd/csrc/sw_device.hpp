@@ -38,7 +38,7 @@ constexpr int kBlock = 256;            // threads per workgroup (4 wave64)
 constexpr int kK3Block = SW_K3_THREADS;  // threads per K3 workgroup
 constexpr uint32_t kTagInit = 0, kTagBond = 1, kTagRefine = 2, kTagFlip = 3;
 
-enum : uint32_t { FLAG_SERIES = 1u, FLAG_KEEP = 2u, FLAG_PCC = 4u };
+enum : uint32_t { FLAG_SERIES = 1u, FLAG_KEEP = 2u, FLAG_PCC = 4u, FLAG_BITPACK = 8u };
 
 // --------------------------------------------------------------------------
 // Replica descriptor (device resident; the host keeps a mirror).
@@ -66,7 +66,8 @@ struct SwRep {
     uint32_t series_cap;        // entries the series buffer holds
     uint32_t trace_cap;         // entries the PCC trace buffers hold
     int32_t active;             // batched mode: replica takes part
-    int8_t* spins;              // N
+    int8_t* spins;              // N int8 +1/-1; with FLAG_BITPACK ceil(N/32) uint32 words instead,
+                                // site i up iff bit i%32 of word i/32 is set
     uint16_t* lab16;            // N tile-local labels (tile-local index of the cluster's tile root)
     int32_t* par;               // N global union-find parents (border roots only)
     int32_t* lab32;             // N final labels (FLAG_KEEP or FLAG_PCC), else null
@@ -483,6 +484,29 @@ __device__ __forceinline__ uint32_t load_part(const int8_t* p, int n, bool wide)
     return m;
 }
 
+// the n <= 32 bits from bit position pos of a packed array (reads the second
+// word only when the bits cross into it, so never past the last site)
+__device__ __forceinline__ uint32_t packed_bits(const uint32_t* w, uint32_t pos, int n)
+{
+    const uint32_t i = pos >> 5, sh = pos & 31u;
+    uint32_t v = w[i] >> sh;
+    if (sh + (uint32_t)n > 32u) v |= w[i + 1] << (32u - sh);
+    return n >= 32 ? v : v & ((1u << n) - 1u);
+}
+
+// up bits of the n <= 16 sites from site index i, int8 or bit-packed
+__device__ __forceinline__ uint32_t load_spins(const SwRep& R, uint32_t i, int n, bool wide)
+{
+    if (R.flags & FLAG_BITPACK) return packed_bits(reinterpret_cast<const uint32_t*>(R.spins), i, n);
+    return load_part(R.spins + i, n, wide);
+}
+
+__device__ __forceinline__ uint32_t spin_up(const SwRep& R, uint32_t i)
+{
+    if (R.flags & FLAG_BITPACK) return (reinterpret_cast<const uint32_t*>(R.spins)[i >> 5] >> (i & 31u)) & 1u;
+    return R.spins[i] > 0;
+}
+
 // bit masks of a row's RQ parts (16 bits at 16q) -> the whole row, in every
 // thread of the row
 template <int RQ>
@@ -571,22 +595,22 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
 
     // 1) spins: the row, the +x halo site, and for the last row in y / z of
     //    the tile the neighbour row beyond it
-    uint32_t mine = partok ? load_part(R.spins + gi0 + (uint32_t)xp, np, wide) : 0u;
+    uint32_t mine = partok ? load_spins(R, gi0 + (uint32_t)xp, np, wide) : 0u;
     const uint64_t S = row_gather<RQ>(mine, q);
     uint32_t hb = 0;
     if (rowok && q == RQ - 1) {
         const uint32_t hx = ((uint32_t)(g.x0 + g.wx) == L) ? 0u : (uint32_t)(g.x0 + g.wx);
-        hb = R.spins[hx + L * (yy + L * zz)] > 0;
+        hb = spin_up(R, hx + L * (yy + L * zz));
     }
     const uint64_t HB = __shfl(hb, (threadIdx.x & 63) | (RQ - 1), 64);
     uint32_t ypart = 0, zpart = 0;
     if (partok && edgeY) {
         const uint32_t ny = (yy + 1u == L) ? 0u : yy + 1u;
-        ypart = load_part(R.spins + (uint32_t)g.x0 + L * (ny + L * zz) + (uint32_t)xp, np, wide);
+        ypart = load_spins(R, (uint32_t)g.x0 + L * (ny + L * zz) + (uint32_t)xp, np, wide);
     }
     if (C::D == 3 && partok && edgeZ) {
         const uint32_t nz = (zz + 1u == L) ? 0u : zz + 1u;
-        zpart = load_part(R.spins + (uint32_t)g.x0 + L * (yy + L * nz) + (uint32_t)xp, np, wide);
+        zpart = load_spins(R, (uint32_t)g.x0 + L * (yy + L * nz) + (uint32_t)xp, np, wide);
     }
     const uint64_t HY = row_gather<RQ>(ypart, q);
     const uint64_t HZ = (C::D == 3) ? row_gather<RQ>(zpart, q) : 0ull;
@@ -1289,6 +1313,7 @@ template <class C>
 struct K3Smem {
     uint32_t FL[C::FBW];         // flip bit of every tile root (from K3a)
     uint32_t FBt[C::FBW];        // the tile's border-root bitmap (labels only)
+    uint32_t wbits[2 * (kK3Block / 64)];   // per wave: bits and set bits of the packed word being written
 };
 
 // new spin byte of the site with tile-local index k and stored label v;
@@ -1332,6 +1357,7 @@ __device__ void k3_lean_tile(const SwRep& R, int t, const TileGeo& g, K3Smem<C>&
     constexpr int GPT = C::TS / W / kK3Block;            // groups per thread (blockDim = kK3Block)
     static_assert(C::TS % (W * kK3Block) == 0, "whole groups per thread");
     static_assert((C::TS & (C::TS - 1)) == 0, "a label masked to TS - 1 stays inside the bitmap");
+    const bool packed = (R.flags & FLAG_BITPACK) != 0;   // then W = 8: one byte of bits per group
     LabV lv[GPT];
     uint32_t gq[GPT];
     bool ok[GPT];
@@ -1354,6 +1380,7 @@ __device__ void k3_lean_tile(const SwRep& R, int t, const TileGeo& g, K3Smem<C>&
         const uint32_t k = (uint32_t)((qd / GR) * C::TX + (qd % GR) * W);
         const uint32_t* lw = reinterpret_cast<const uint32_t*>(&lv[j]);   // two labels per word
         uint32_t out[W / 4];
+        uint32_t pb = 0;                                  // the group's new spins as bits
 #pragma unroll
         for (int h = 0; h < W / 4; ++h) {
             out[h] = 0;
@@ -1365,11 +1392,73 @@ __device__ void k3_lean_tile(const SwRep& R, int t, const TileGeo& g, K3Smem<C>&
                 const uint32_t lr = lab & (uint32_t)(C::TS - 1);
                 const uint32_t bit = (sm.FL[lr >> 5] >> (lr & 31u)) & 1u;
                 out[h] |= (bit ? 0x01u : 0xFFu) << (8 * i);
+                pb |= bit << n;
             }
         }
-        if (ok[j]) *reinterpret_cast<SpinV*>(R.spins + gq[j]) = *reinterpret_cast<const SpinV*>(out);
+        if (ok[j]) {
+            if (packed)   // W = 8 sites from a multiple of 8: one byte of the packed array, owned by this tile
+                reinterpret_cast<uint8_t*>(R.spins)[gq[j] >> 3] = (uint8_t)pb;
+            else
+                *reinterpret_cast<SpinV*>(R.spins + gq[j]) = *reinterpret_cast<const SpinV*>(out);
+        }
     }
     if (bad) flag_error(R, ERR_TILE_LABEL);
+    __syncthreads();
+}
+
+// The new spins of a bit-packed lattice, one site per thread: the bits of one
+// 32-bit word are combined over the wave, and the word is updated with an
+// atomic AND of its cleared bits then an OR of its set bits, so that tiles
+// whose sites share a word (rows that are not whole words) never overwrite
+// each other's bits.  All lanes of the wave call it.
+__device__ __forceinline__ void wave_set_bits(uint32_t* words, uint32_t site, uint32_t up, bool pending, uint32_t* wscr)
+{
+    const int lane = threadIdx.x & 63;
+    while (true) {
+        const uint64_t bal = __ballot(pending);
+        if (!bal) break;
+        const int first = __builtin_ctzll(bal);
+        const uint32_t lead = __shfl(site >> 5, first, 64);
+        bool leader = false;
+        if (pending && (site >> 5) == lead) {
+            atomicOr(&wscr[0], 1u << (site & 31u));
+            if (up) atomicOr(&wscr[1], 1u << (site & 31u));
+            pending = false;
+            leader = lane == first;
+        }
+        wave_lds_sync();
+        if (leader) {
+            const uint32_t m = wscr[0], v = wscr[1];
+            if (m & ~v) atomicAnd(&words[lead], ~(m & ~v));
+            if (v) atomicOr(&words[lead], v);
+            wscr[0] = wscr[1] = 0;
+        }
+        wave_lds_sync();
+    }
+}
+
+template <class C>
+__device__ void k3_packed_tile(const SwRep& R, int t, const TileGeo& g, K3Smem<C>& sm, bool labels)
+{
+    const int tid = threadIdx.x;
+    const uint32_t L = (uint32_t)R.L;
+    if (tid < 2 * (kK3Block / 64)) sm.wbits[tid] = 0;
+    for (int w = tid; w < C::FBW; w += blockDim.x) {
+        sm.FL[w] = R.bflip[(size_t)t * C::FBW + w];
+        if (labels) sm.FBt[w] = R.fbits[(size_t)t * C::FBW + w];
+    }
+    __syncthreads();
+    uint32_t* words = reinterpret_cast<uint32_t*>(R.spins);
+    for (int k0 = 0; k0 < C::TS; k0 += kK3Block) {     // every lane of a wave runs the same iterations
+        const int k = k0 + tid;
+        const int xk = k % C::TX, r = k / C::TX;
+        const int ly = r % C::TY, lz = r / C::TY;
+        const bool valid = ly < g.wy && lz < g.wz && xk < g.wx;
+        const uint32_t gi = (uint32_t)(g.x0 + xk) + L * ((uint32_t)(g.y0 + ly) + L * (uint32_t)(g.z0 + lz));
+        uint32_t up = 0;
+        if (valid) up = k3_site<C>(R, sm, g, R.lab16[gi], k, gi, labels) == 0x01u;
+        wave_set_bits(words, gi, up, valid, &sm.wbits[2 * (tid >> 6)]);
+    }
     __syncthreads();
 }
 
@@ -1383,10 +1472,15 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
     const bool labels = R.lab32 != nullptr;
     constexpr int QR = C::TX / 4;                       // quads of sites per row
     constexpr int QPT = C::TS / 4 / kK3Block;           // quads per thread (blockDim = kK3Block)
+    const bool packed = (R.flags & FLAG_BITPACK) != 0;
     const bool quads = (L & 3u) == 0;                   // then every row and the tile width are multiples of 4
-    if (!labels && quads) {
+    if (!labels && quads && (!packed || (L & 7u) == 0)) {
         if ((L & 7u) == 0) k3_lean_tile<C, 8>(R, t, g, sm);
         else k3_lean_tile<C, 4>(R, t, g, sm);
+        return;
+    }
+    if (packed) {                                        // labels, or rows that are not whole bytes of bits
+        k3_packed_tile<C>(R, t, g, sm, labels);
         return;
     }
 

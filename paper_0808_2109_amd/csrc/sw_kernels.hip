@@ -212,15 +212,16 @@ __device__ void measure_range(const SwRep& R, uint32_t i0, uint32_t i1, uint32_t
 {
     const uint32_t L = (uint32_t)R.L;
     const uint32_t LL = L * L;
+    auto sp = [&](uint32_t j) { return 2 * (int)spin_up(R, j) - 1; };
     for (uint32_t i = i0; i < i1; i += stride) {
-        const int sv = R.spins[i];
+        const int sv = sp(i);
         const uint32_t x = i % L;
         const uint32_t y = (i / L) % L;
-        int nb = R.spins[(x == L - 1) ? i - (L - 1) : i + 1];
-        nb += R.spins[(y == L - 1) ? i - (L - 1) * L : i + L];
+        int nb = sp((x == L - 1) ? i - (L - 1) : i + 1);
+        nb += sp((y == L - 1) ? i - (L - 1) * L : i + L);
         if (R.dim == 3) {
             const uint32_t z = i / LL;
-            nb += R.spins[(z == L - 1) ? i - (L - 1) * LL : i + LL];
+            nb += sp((z == L - 1) ? i - (L - 1) * LL : i + LL);
         }
         m += sv;
         e += sv * nb;
@@ -240,10 +241,23 @@ __global__ __launch_bounds__(kBlock) void kmeasure_kernel(const SwRep* Rd, int64
     }
 }
 
-// initial spins: site i is up when bit i%32 of word (i>>5)%4 of Philox(i>>7, 0, 0, INIT) is set
+// initial spins: site i is up when bit i%32 of word (i>>5)%4 of Philox(i>>7, 0, 0, INIT) is set.
+// Bit-packed, word w of the lattice is word w%4 of block w>>2 (the bits past
+// site N-1 cleared).
 __global__ __launch_bounds__(kBlock) void kinit_kernel(const SwRep* Rd)
 {
     const SwRep R = *Rd;
+    if (R.flags & FLAG_BITPACK) {
+        const uint32_t nw = (R.N + 31u) / 32u;
+        uint32_t* words = reinterpret_cast<uint32_t*>(R.spins);
+        for (uint32_t w = blockIdx.x * kBlock + threadIdx.x; w < nw; w += gridDim.x * kBlock) {
+            const U4 r = philox10(w >> 2, 0u, 0u, kTagInit, (uint32_t)R.seed, (uint32_t)(R.seed >> 32));
+            uint32_t v = pick(r, w & 3u);
+            if (w == nw - 1u && (R.N & 31u)) v &= (1u << (R.N & 31u)) - 1u;
+            words[w] = v;
+        }
+        return;
+    }
     const uint32_t nblk = (R.N + 127u) / 128u;
     for (uint32_t b = blockIdx.x * kBlock + threadIdx.x; b < nblk; b += gridDim.x * kBlock) {
         const U4 r = philox10(b, 0u, 0u, kTagInit, (uint32_t)R.seed, (uint32_t)(R.seed >> 32));

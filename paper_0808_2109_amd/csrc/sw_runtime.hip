@@ -93,7 +93,8 @@ int validate_params(const sw_params* p)
     } else if (!(p->p_bond <= 1.0)) {
         return fail(SW_EINVAL, "p_bond must be in [0,1] or negative");
     }
-    if (p->flags & ~(uint32_t)(SW_RECORD_SERIES | SW_KEEP_LABELS | SW_PCC)) return fail(SW_EINVAL, "unknown flags");
+    if (p->flags & ~(uint32_t)(SW_RECORD_SERIES | SW_KEEP_LABELS | SW_PCC | SW_BITPACK))
+        return fail(SW_EINVAL, "unknown flags");
     if (p->flags & SW_PCC) {
         if (!(p->pcc_dp0 > 0.0) || !std::isfinite(p->pcc_dp0)) return fail(SW_EINVAL, "pcc_dp0 must be > 0");
         if (p->pcc_halve_every == 0) return fail(SW_EINVAL, "pcc_halve_every must be > 0");
@@ -138,6 +139,12 @@ static uint64_t tile_bytes(const SwRep& h, bool pcc)
     return b;
 }
 
+// bytes of a replica's spin array: N int8, or ceil(N/32) words bit-packed
+size_t spin_bytes(const SwRep& h)
+{
+    return (h.flags & FLAG_BITPACK) ? ((size_t)h.N + 31) / 32 * 4 : (size_t)h.N;
+}
+
 uint64_t footprint_bytes(const sw_params* p, int shape)
 {
     const uint64_t n = nsites_of(p);
@@ -145,7 +152,8 @@ uint64_t footprint_bytes(const sw_params* p, int shape)
     h.dim = p->dim;
     h.L = p->L;
     fill_geometry(h, shape);
-    uint64_t b = n * (1 + 2 + 4);                            // spins, lab16, par
+    uint64_t b = n * (2 + 4);                                // lab16, par
+    b += (p->flags & SW_BITPACK) ? (n + 31) / 32 * 4 : n;    // spins
     if (p->flags & SW_KEEP_LABELS) b += 4 * n;               // lab32
     b += tile_bytes(h, (p->flags & SW_PCC) != 0);            // crossing bits, bitmaps, face labels, coverage
     b += 64;                                                 // accumulators
@@ -250,6 +258,7 @@ int replica_alloc(ReplicaH& r, const sw_params* p, int shape, hipStream_t stream
     if (p->flags & SW_RECORD_SERIES) h.flags |= FLAG_SERIES;
     if (p->flags & SW_KEEP_LABELS) h.flags |= FLAG_KEEP;
     if (p->flags & SW_PCC) h.flags |= FLAG_PCC;
+    if (p->flags & SW_BITPACK) h.flags |= FLAG_BITPACK;
     h.seed = p->seed;
     h.p = (p->p_bond < 0.0) ? -std::expm1(-2.0 * p->J / p->T) : p->p_bond;
     h.thr = threshold_from_p(h.p);
@@ -262,7 +271,7 @@ int replica_alloc(ReplicaH& r, const sw_params* p, int shape, hipStream_t stream
     const size_t n = h.N;
     int rc;
     r.own_spins = true;
-    if ((rc = dmalloc((void**)&h.spins, n, "spins"))) goto bad;
+    if ((rc = dmalloc((void**)&h.spins, spin_bytes(h), "spins"))) goto bad;
     if ((rc = dmalloc((void**)&h.lab16, 2 * n, "tile labels"))) goto bad;
     if ((rc = dmalloc((void**)&h.par, 4 * n, "union-find parents"))) goto bad;
     if (h.flags & FLAG_KEEP)
@@ -298,6 +307,34 @@ int replica_alloc(ReplicaH& r, const sw_params* p, int shape, hipStream_t stream
 bad:
     replica_free(r);
     return rc;
+}
+
+// the N spins of a replica as int8 +1/-1 in host memory (a bit-packed array
+// is unpacked here; the device holds only the packed words)
+int read_spins(const SwRep& m, int8_t* host_buf)
+{
+    if (!(m.flags & FLAG_BITPACK)) {
+        hipError_t e = hipMemcpy(host_buf, m.spins, m.N, hipMemcpyDeviceToHost);
+        return e == hipSuccess ? SW_OK : hip_fail(e, "reading spins");
+    }
+    std::vector<uint32_t> w(((size_t)m.N + 31) / 32);
+    hipError_t e = hipMemcpy(w.data(), m.spins, w.size() * 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "reading spins");
+    for (size_t i = 0; i < m.N; ++i) host_buf[i] = ((w[i >> 5] >> (i & 31)) & 1u) ? 1 : -1;
+    return SW_OK;
+}
+
+static int write_spins(const SwRep& m, const int8_t* host_buf)
+{
+    if (!(m.flags & FLAG_BITPACK)) {
+        hipError_t e = hipMemcpy(m.spins, host_buf, m.N, hipMemcpyHostToDevice);
+        return e == hipSuccess ? SW_OK : hip_fail(e, "writing spins");
+    }
+    std::vector<uint32_t> w(((size_t)m.N + 31) / 32, 0u);
+    for (size_t i = 0; i < m.N; ++i)
+        if (host_buf[i] > 0) w[i >> 5] |= 1u << (i & 31);
+    hipError_t e = hipMemcpy(m.spins, w.data(), w.size() * 4, hipMemcpyHostToDevice);
+    return e == hipSuccess ? SW_OK : hip_fail(e, "writing spins");
 }
 
 static int check_rep(sw_lattice* h, int32_t r)
@@ -854,8 +891,7 @@ int sw_get_spins(sw_lattice* h, int32_t replica, int8_t* host_buf, int64_t cap)
     rc = set_device(h);
     if (!rc) rc = handle_sync(h);
     if (rc) return rc;
-    hipError_t e = hipMemcpy(host_buf, m.spins, m.N, hipMemcpyDeviceToHost);
-    return e == hipSuccess ? SW_OK : hip_fail(e, "reading spins");
+    return read_spins(m, host_buf);
 }
 
 int sw_get_labels(sw_lattice* h, int32_t replica, int32_t* host_buf, int64_t cap)
@@ -929,8 +965,8 @@ int sw_set_spins(sw_lattice* h, int32_t replica, const int8_t* host_buf, int64_t
     rc = set_device(h);
     if (!rc) rc = sync_mirror(h);
     if (rc) return rc;
-    hipError_t e = hipMemcpy(m.spins, host_buf, (size_t)n, hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "writing spins");
+    rc = write_spins(m, host_buf);
+    if (rc) return rc;
     // The records restart at the resume point.  Series rows are accumulated
     // with atomic adds, so the reused rows are cleared; PCC candidate marks
     // carry the tag of the sweep that wrote them, and a tag left by a later

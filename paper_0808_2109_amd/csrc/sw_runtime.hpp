@@ -36,6 +36,8 @@ uint64_t nsites_of(const sw_params* p);
 int default_shape(int dim);
 void fill_geometry(SwRep& h, int shape);
 uint64_t footprint_bytes(const sw_params* p, int shape);
+size_t spin_bytes(const SwRep& h);
+int read_spins(const SwRep& m, int8_t* host_buf);
 int replica_alloc(ReplicaH& r, const sw_params* p, int shape, hipStream_t stream);
 void replica_free(ReplicaH& r);
 

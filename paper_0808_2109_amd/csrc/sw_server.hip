@@ -147,8 +147,8 @@ static int retire(sw_server* s)
         rc = sw_measure(s->lat, k, &j.e_int, &j.m);
         if (rc) return rc;
         std::vector<int8_t> sp(r.h.N);
-        hipError_t e = hipMemcpy(sp.data(), r.h.spins, r.h.N, hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return hip_fail(e, "reading a finished job's spins");
+        rc = read_spins(r.h, sp.data());
+        if (rc) return rc;
         j.hash = fnv1a(sp.data(), sp.size());
         if (r.h.N <= kKeepSpins) j.spins.swap(sp);
         j.state = SW_JOB_DONE;
