@@ -85,6 +85,18 @@ def _load():
                             c.POINTER(c.c_uint64), c.POINTER(c.c_double), c.c_int, c.c_double,
                             c.c_uint32, INT8P, c.c_void_p, c.c_void_p, c.c_void_p, c.c_void_p]
     lib.orc_run.restype = c.c_int
+    lib.orc_bonds_open.argtypes = [c.c_int, c.c_int, c.c_uint64, c.c_uint32, c.c_uint64, INT8P, UINT8P]
+    lib.orc_bonds_open.restype = None
+    lib.orc_measure_open.argtypes = [c.c_int, c.c_int, INT8P, c.POINTER(c.c_int64), c.POINTER(c.c_int64)]
+    lib.orc_measure_open.restype = None
+    lib.orc_spans_open.argtypes = [c.c_int, c.c_int, INT32P]
+    lib.orc_spans_open.restype = c.c_int
+    lib.orc_winds.argtypes = [c.c_int, c.c_int, UINT8P]
+    lib.orc_winds.restype = c.c_int
+    lib.orc_run_bc.argtypes = [c.c_int, c.c_int, c.c_uint64, c.c_uint32, c.c_int32,
+                               c.POINTER(c.c_uint64), c.POINTER(c.c_double), c.c_int, c.c_double,
+                               c.c_uint32, INT8P, c.c_void_p, c.c_void_p, c.c_void_p, c.c_void_p]
+    lib.orc_run_bc.restype = c.c_int
     _lib = lib
     return lib
 
@@ -148,6 +160,35 @@ def bonds(dim: int, L: int, seed: int, sweep: int, thr: int, spins: np.ndarray) 
     return out.reshape(dim, n)
 
 
+def bonds_open(dim: int, L: int, seed: int, sweep: int, thr: int, spins: np.ndarray) -> np.ndarray:
+    """Bond array with open boundaries: the links that would wrap are absent (0)."""
+    n = nsites(dim, L)
+    out = np.zeros(dim * n, dtype=np.uint8)
+    _load().orc_bonds_open(dim, L, seed, sweep, thr, np.ascontiguousarray(spins, dtype=np.int8), out)
+    return out.reshape(dim, n)
+
+
+def measure_open(dim: int, L: int, spins: np.ndarray):
+    e = ctypes.c_int64()
+    m = ctypes.c_int64()
+    _load().orc_measure_open(dim, L, np.ascontiguousarray(spins, dtype=np.int8), ctypes.byref(e), ctypes.byref(m))
+    return int(e.value), int(m.value)
+
+
+def spans_open(dim: int, L: int, labels: np.ndarray) -> bool:
+    rc = _load().orc_spans_open(dim, L, np.ascontiguousarray(labels, dtype=np.int32))
+    if rc < 0:
+        raise MemoryError("oracle spanning test failed")
+    return bool(rc)
+
+
+def winds(dim: int, L: int, open_: np.ndarray) -> bool:
+    rc = _load().orc_winds(dim, L, np.ascontiguousarray(open_.reshape(-1), dtype=np.uint8))
+    if rc < 0:
+        raise MemoryError("oracle winding test failed")
+    return bool(rc)
+
+
 def label_bfs(dim: int, L: int, open_: np.ndarray) -> np.ndarray:
     n = nsites(dim, L)
     lab = np.empty(n, dtype=np.int32)
@@ -198,11 +239,13 @@ def pcc_update(p: float, thr: int, percolating: bool, sweep_index: int,
 def run(dim: int, L: int, seed: int, nsweeps: int, *, thr: int | None = None, J: float = 1.0,
         T: float | None = None, p: float | None = None, s0: int = 0, spins: np.ndarray | None = None,
         pcc: bool = False, dp0: float = 0.01, halve_every: int = 1000,
-        record_series: bool = True, keep_labels: bool = True):
+        record_series: bool = True, keep_labels: bool = True, open_bc: bool = False, wind: bool = False):
     """Run `nsweeps` sweeps from sweep index s0.
 
     Returns a dict with spins, series (nsweeps x 2 of E_int, M), labels of the
     last sweep, and for pcc the percolation flags, the p trace and final p/thr.
+    open_bc: open boundaries (PCC spanning: both opposite boundaries of an axis);
+    wind: the topological rule instead of the extension rule (periodic only).
     """
     n = nsites(dim, L)
     if spins is None:
@@ -222,8 +265,9 @@ def run(dim: int, L: int, seed: int, nsweeps: int, *, thr: int | None = None, J:
     def ptr_of(a):
         return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
-    rc = _load().orc_run(dim, L, seed, s0, nsweeps, ctypes.byref(tt), ctypes.byref(pp), int(pcc),
-                         dp0, halve_every, s, ptr_of(series), ptr_of(labels), ptr_of(perc), ptr_of(ptr))
+    mode = (1 if pcc else 0) | (2 if open_bc else 0) | (4 if wind else 0)
+    rc = _load().orc_run_bc(dim, L, seed, s0, nsweeps, ctypes.byref(tt), ctypes.byref(pp), mode,
+                            dp0, halve_every, s, ptr_of(series), ptr_of(labels), ptr_of(perc), ptr_of(ptr))
     if rc != 0:
         raise ValueError("oracle run failed (invalid parameters or out of memory)")
     return {"spins": s, "series": series, "labels": labels, "perc": perc, "p_trace": ptr,

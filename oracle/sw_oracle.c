@@ -1,8 +1,9 @@
 /*
  * sw_oracle.c -- plain, sequential CPU oracle for one Swendsen-Wang sweep of
  * the Ising model H = -J sum_<ij> s_i s_j (Lin & Zheng, Sec. I, steps 1-4) and
- * for the probability-changing-cluster feedback with the extension rule
- * (Sec. III).
+ * for the probability-changing-cluster feedback (Sec. III) with its
+ * percolation tests: the extension rule and the topological (winding) rule on
+ * periodic boxes, and the spanning test of open boxes.
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the reference that the GPU library
  * is checked against.  Only the test suite, the smoke check and the CPU
@@ -13,6 +14,10 @@
  *
  * Everything is deliberately unoptimised: one Philox call per link, one byte
  * per bond, breadth-first search for the clusters.
+ *
+ * Boundary conditions: periodic in every axis, or open (Sec. III discusses
+ * both): with open boundaries the links that would wrap around the box do not
+ * exist; every other link keeps its index and so its random draw.
  *
  * Conventions (the paper is silent on them; the readings are listed in the
  * design notes):
@@ -196,6 +201,27 @@ void orc_bonds(int dim, int L, uint64_t seed, uint32_t sweep, uint64_t thr,
     }
 }
 
+/* The same with open boundaries: a link that would wrap around the box (from
+ * coordinate L-1 along its axis) does not exist and is never a bond. */
+void orc_bonds_open(int dim, int L, uint64_t seed, uint32_t sweep, uint64_t thr,
+                    const int8_t *spins, uint8_t *open)
+{
+    int64_t n = orc_nsites(dim, L);
+    int64_t stride = 1;
+    for (int d = 0; d < dim; ++d) {
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t l = (int64_t)d * n + i;
+            if ((i / stride) % L == L - 1) {
+                open[l] = 0;
+                continue;
+            }
+            int64_t j = i + stride;
+            open[l] = (uint8_t)orc_bond_open(seed, sweep, thr, (uint32_t)l, spins[i] == spins[j]);
+        }
+        stride *= L;
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Step 2: clusters.  Visiting sites in increasing index order and flooding  */
 /* each unvisited one breadth-first labels every cluster with the smallest  */
@@ -256,6 +282,23 @@ void orc_measure(int dim, int L, const int8_t *spins, int64_t *e_int, int64_t *m
     for (int64_t i = 0; i < n; ++i) {
         mm += spins[i];
         for (int d = 0; d < dim; ++d) e += (int64_t)spins[i] * spins[orc_forward(dim, L, i, d)];
+    }
+    *e_int = e;
+    *m = mm;
+}
+
+/* With open boundaries E_int sums over the existing links only. */
+void orc_measure_open(int dim, int L, const int8_t *spins, int64_t *e_int, int64_t *m)
+{
+    int64_t n = orc_nsites(dim, L);
+    int64_t e = 0, mm = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        mm += spins[i];
+        int64_t stride = 1;
+        for (int d = 0; d < dim; ++d) {
+            if ((i / stride) % L != L - 1) e += (int64_t)spins[i] * spins[i + stride];
+            stride *= L;
+        }
     }
     *e_int = e;
     *m = mm;
@@ -323,6 +366,82 @@ int orc_percolates(int dim, int L, const int32_t *labels)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Spanning with open boundaries (Sec. III): the configuration percolates    */
+/* when one cluster occupies both opposite boundaries of some axis, the      */
+/* sites with coordinate 0 and the sites with coordinate L-1.                */
+/* Returns 1 / 0, or -1 on allocation failure.                                */
+/* ------------------------------------------------------------------------ */
+int orc_spans_open(int dim, int L, const int32_t *labels)
+{
+    int64_t n = orc_nsites(dim, L);
+    uint8_t *low = (uint8_t *)malloc((size_t)n);     /* label touches coordinate 0 of the axis */
+    if (!low) return -1;
+    int result = 0;
+    int64_t stride = 1;
+    for (int axis = 0; axis < dim && !result; ++axis) {
+        memset(low, 0, (size_t)n);
+        for (int64_t i = 0; i < n; ++i)
+            if ((i / stride) % L == 0) low[labels[i]] = 1;
+        for (int64_t i = 0; i < n && !result; ++i)
+            if ((i / stride) % L == L - 1 && low[labels[i]]) result = 1;
+        stride *= L;
+    }
+    free(low);
+    return result;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Topological rule (Sec. III): the configuration percolates when one        */
+/* cluster winds around the periodic box along some axis.  Each cluster is   */
+/* searched breadth-first from its smallest site, giving every site reached  */
+/* an unwrapped position (a step along a link moves one unit along its axis, */
+/* whether or not the link wraps around the box).  A link that reaches a     */
+/* site already placed at a different unwrapped position closes a loop that  */
+/* goes around the box: its positions differ by a nonzero multiple of L.     */
+/* Returns 1 / 0, or -1 on allocation failure.                                */
+/* ------------------------------------------------------------------------ */
+int orc_winds(int dim, int L, const uint8_t *open)
+{
+    int64_t n = orc_nsites(dim, L);
+    int64_t *pos = (int64_t *)malloc((size_t)n * 3 * sizeof(int64_t));
+    uint8_t *seen = (uint8_t *)calloc((size_t)n, 1);
+    int64_t *queue = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    if (!pos || !seen || !queue) {
+        free(pos); free(seen); free(queue);
+        return -1;
+    }
+    int result = 0;
+    for (int64_t start = 0; start < n && !result; ++start) {
+        if (seen[start]) continue;
+        int64_t head = 0, tail = 0;
+        seen[start] = 1;
+        for (int d = 0; d < 3; ++d) pos[3 * start + d] = 0;
+        queue[tail++] = start;
+        while (head < tail && !result) {
+            int64_t u = queue[head++];
+            for (int d = 0; d < dim && !result; ++d) {
+                for (int dir = 0; dir < 2 && !result; ++dir) {
+                    int64_t v = dir ? orc_forward(dim, L, u, d) : orc_backward(dim, L, u, d);
+                    int64_t link = dir ? (int64_t)d * n + u : (int64_t)d * n + v;
+                    if (!open[link]) continue;
+                    int64_t want[3] = {pos[3 * u], pos[3 * u + 1], pos[3 * u + 2]};
+                    want[d] += dir ? 1 : -1;
+                    if (!seen[v]) {
+                        seen[v] = 1;
+                        for (int k = 0; k < 3; ++k) pos[3 * v + k] = want[k];
+                        queue[tail++] = v;
+                    } else if (pos[3 * v] != want[0] || pos[3 * v + 1] != want[1] || pos[3 * v + 2] != want[2]) {
+                        result = 1;
+                    }
+                }
+            }
+        }
+    }
+    free(pos); free(seen); free(queue);
+    return result;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Feedback on the bond probability after sweep `sweep` (PCC, Sec. I and     */
 /* Sec. III): p -= dp when percolating, p += dp otherwise, with              */
 /* dp = dp0 * 2^-(sweep / halve_every), clamped to [0, 1]; the threshold of  */
@@ -348,6 +467,54 @@ void orc_pcc_update(double *p, uint64_t *thr, int percolating, uint32_t sweep,
 /* With pcc != 0 the threshold follows the feedback rule, starting from      */
 /* *thr / *p; otherwise *thr is used unchanged.  Returns 0 or -1.             */
 /* ------------------------------------------------------------------------ */
+/* mode bits of orc_run_bc */
+#define ORC_PCC 1      /* PCC feedback                                          */
+#define ORC_OPEN 2     /* open boundaries (spanning: both opposite boundaries)  */
+#define ORC_WIND 4     /* topological rule (periodic boundaries only)           */
+
+/* As orc_run, with the boundary conditions and the percolation rule chosen by
+ * `mode`: periodic boundaries take the extension rule, or with ORC_WIND the
+ * topological rule; open boundaries take the spanning test of the open box. */
+int orc_run_bc(int dim, int L, uint64_t seed, uint32_t s0, int32_t nsweeps,
+               uint64_t *thr, double *p, int mode, double dp0, uint32_t halve_every,
+               int8_t *spins, int64_t *series, int32_t *labels, int32_t *perc, double *p_trace)
+{
+    if (orc_validate(dim, L) != 0 || nsweeps < 0) return -1;
+    if ((mode & ORC_PCC) && halve_every == 0) return -1;
+    if ((mode & ORC_OPEN) && (mode & ORC_WIND)) return -1;
+    int64_t n = orc_nsites(dim, L);
+    int32_t *lab = labels ? labels : (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    uint8_t *open = (uint8_t *)malloc((size_t)(dim * n));
+    if (!lab || !open) {
+        if (!labels) free(lab);
+        free(open);
+        return -1;
+    }
+    int rc = 0;
+    for (int32_t k = 0; k < nsweeps; ++k) {
+        uint32_t sweep = s0 + (uint32_t)k;
+        if (mode & ORC_OPEN) orc_bonds_open(dim, L, seed, sweep, *thr, spins, open);
+        else orc_bonds(dim, L, seed, sweep, *thr, spins, open);
+        if (orc_label_bfs(dim, L, open, lab) < 0) { rc = -1; break; }
+        orc_flip(dim, L, seed, sweep, lab, spins);
+        if (series) {
+            if (mode & ORC_OPEN) orc_measure_open(dim, L, spins, &series[2 * k], &series[2 * k + 1]);
+            else orc_measure(dim, L, spins, &series[2 * k], &series[2 * k + 1]);
+        }
+        if (mode & ORC_PCC) {
+            int pc = (mode & ORC_OPEN) ? orc_spans_open(dim, L, lab)
+                     : (mode & ORC_WIND) ? orc_winds(dim, L, open) : orc_percolates(dim, L, lab);
+            if (pc < 0) { rc = -1; break; }
+            if (perc) perc[k] = pc;
+            orc_pcc_update(p, thr, pc, sweep, dp0, halve_every);
+            if (p_trace) p_trace[k] = *p;
+        }
+    }
+    if (!labels) free(lab);
+    free(open);
+    return rc;
+}
+
 int orc_run(int dim, int L, uint64_t seed, uint32_t s0, int32_t nsweeps,
             uint64_t *thr, double *p, int pcc, double dp0, uint32_t halve_every,
             int8_t *spins, int64_t *series, int32_t *labels, int32_t *perc, double *p_trace)

@@ -142,3 +142,15 @@ def kaufman_energy(L: int, T: float, J: float = 1.0, digits: int = 40) -> float:
 def yang_magnetisation(T: float, J: float = 1.0) -> float:
     """Spontaneous magnetisation of the infinite square lattice (C. N. Yang, 1952)."""
     return (1.0 - math.sinh(2.0 * J / T) ** -4) ** 0.125
+
+
+def histogram_2d_open(L: int):
+    """Joint histogram {(E_int, M): count} of the L x L lattice with open
+    boundaries (only the 2 L (L - 1) links inside the box), L <= 5."""
+    n = L * L
+    states = np.arange(1 << n, dtype=np.int64)
+    s = _bits(states, n).reshape(-1, L, L)          # [state, y, x]
+    e = (s[:, :, :-1] * s[:, :, 1:]).sum(axis=(1, 2)) + (s[:, :-1, :] * s[:, 1:, :]).sum(axis=(1, 2))
+    m = s.sum(axis=(1, 2))
+    keys, counts = np.unique(np.stack([e, m], axis=1), axis=0, return_counts=True)
+    return {(int(a), int(b)): int(c) for (a, b), c in zip(keys, counts)}
