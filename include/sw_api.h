@@ -12,7 +12,7 @@
  * swept together by one hipGraph launch, and a continuous-batching job server.
  *
  * Conventions shared by every entry point
- *   - Lattices are periodic, dim 2 or 3, N = L^dim sites, site index
+ *   - Lattices are periodic (open with SW_OPEN), dim 2 or 3, N = L^dim sites, site index
  *     i = x + L*y (+ L*L*z), x fastest.  Link (i,d) joins i and i + e_d.
  *   - Spins are int8 +1/-1.  Labels are int32: the canonical label of a
  *     cluster is the smallest site index it contains.
@@ -67,11 +67,18 @@ enum {
     SW_RECORD_SERIES = 1u << 0, /* record (E_int, M) after every sweep          */
     SW_KEEP_LABELS = 1u << 1,   /* keep the int32 labels of the last sweep       */
     SW_PCC = 1u << 2,           /* probability-changing-cluster feedback (Sec. III) */
-    SW_BITPACK = 1u << 3        /* keep the spins (the +-1 of Sec. I) as one bit per
+    SW_BITPACK = 1u << 3,       /* keep the spins (the +-1 of Sec. I) as one bit per
                                    site on the device: ceil(N/32) uint32 words, site
                                    i up iff bit i%32 of word i/32 is set.  Every
                                    result is the same as with int8 spins; sw_get_spins
                                    and sw_set_spins still take int8 arrays. */
+    SW_OPEN = 1u << 4           /* open boundaries in every axis (Sec. III discusses
+                                   both kinds): the links that would wrap around the
+                                   box do not exist (every other link keeps its index
+                                   and draw), E_int sums over the box's links, and the
+                                   PCC test is the open box's spanning test: one
+                                   cluster holds sites of both opposite faces
+                                   (coordinate 0 and L-1) of some axis. */
 };
 
 /* execution modes of a multi-replica handle (sw_set_mode) */
@@ -89,7 +96,7 @@ enum {
  *   p_bond          < 0: P = 1 - exp(-2J/T) (evaluated as -expm1(-2J/T) in double);
  *                   in [0,1]: use this P directly (the PCC start value)
  *   seed            key of the random stream
- *   flags           SW_RECORD_SERIES | SW_KEEP_LABELS | SW_PCC | SW_BITPACK
+ *   flags           SW_RECORD_SERIES | SW_KEEP_LABELS | SW_PCC | SW_BITPACK | SW_OPEN
  *   pcc_dp0         PCC step dp at sweep 0 (> 0)
  *   pcc_halve_every dp is halved every this many sweeps (> 0)
  *   series_cap      capacity of the (E_int, M) series in sweeps (0: grows on demand)

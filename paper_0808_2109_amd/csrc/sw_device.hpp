@@ -38,7 +38,7 @@ constexpr int kBlock = 256;            // threads per workgroup (4 wave64)
 constexpr int kK3Block = SW_K3_THREADS;  // threads per K3 workgroup
 constexpr uint32_t kTagInit = 0, kTagBond = 1, kTagRefine = 2, kTagFlip = 3;
 
-enum : uint32_t { FLAG_SERIES = 1u, FLAG_KEEP = 2u, FLAG_PCC = 4u, FLAG_BITPACK = 8u };
+enum : uint32_t { FLAG_SERIES = 1u, FLAG_KEEP = 2u, FLAG_PCC = 4u, FLAG_BITPACK = 8u, FLAG_OPEN = 16u };
 
 // --------------------------------------------------------------------------
 // Replica descriptor (device resident; the host keeps a mirror).
@@ -624,17 +624,25 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
     }
     __syncthreads();
 
-    // 2) bonds of the row's own links (x, d), each thread those of its part
+    // 2) bonds of the row's own links (x, d), each thread those of its part.
+    //    With open boundaries the links that would wrap around the box do not
+    //    exist (ex[d]): they never bond and are left out of E_int.
     uint64_t opn[3] = {0, 0, 0};
     {
         uint64_t eq[3] = {0, 0, 0};
+        uint64_t ex[3] = {lbw, lbw, lbw};
+        if (R.flags & FLAG_OPEN) {
+            if ((uint32_t)(g.x0 + g.wx) == L) ex[0] &= ~(1ull << (g.wx - 1));
+            if (yy == L - 1u) ex[1] = 0;
+            if (C::D == 3 && zz == L - 1u) ex[2] = 0;
+        }
         if (rowok) {
-            eq[0] = ~(S ^ ((S >> 1) | (HB << (g.wx - 1)))) & lbw;
+            eq[0] = ~(S ^ ((S >> 1) | (HB << (g.wx - 1)))) & ex[0];
             const uint64_t nbY = edgeY ? HY : sm.S[min(r + 1, C::NR - 1)];
-            eq[1] = ~(S ^ nbY) & lbw;
+            eq[1] = ~(S ^ nbY) & ex[1];
             if (C::D == 3) {
                 const uint64_t nbZ = edgeZ ? HZ : sm.S[min(r + C::TY, C::NR - 1)];
-                eq[2] = ~(S ^ nbZ) & lbw;
+                eq[2] = ~(S ^ nbZ) & ex[2];
             }
         }
         const uint32_t t_hi = (uint32_t)(thr >> 24);
@@ -667,7 +675,7 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
             const uint64_t pm = low_bits(np) << xp;
             m_acc += 2 * (int)__popcll(S & pm) - np;         // __popcll is unsigned
 #pragma unroll
-            for (int d = 0; d < C::D; ++d) e_acc += 2 * (int)__popcll(eq[d] & pm) - np;
+            for (int d = 0; d < C::D; ++d) e_acc += 2 * (int)__popcll(eq[d] & pm) - (int)__popcll(ex[d] & pm);
         }
     }
     // the x-bond of x = wx-1 leaves the tile: shifted out by the mask

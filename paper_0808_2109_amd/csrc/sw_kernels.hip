@@ -139,7 +139,8 @@ __global__ __launch_bounds__(kBlock) void kcand_kernel(const SwRep* Rd, uint32_t
 // coverage test of the candidates' bitmaps (slots [c0, c1) of every axis);
 // the bitmaps are cleared for the next sweep.  One wave per slot: its lanes
 // read consecutive bitmap words, and a ballot tells whether every coordinate
-// is covered.
+// is covered (periodic box, extension rule) or, for an open box, whether the
+// candidate (which touches coordinate 0) also touches coordinate L - 1.
 __device__ void perc_chunk(const SwRep& R, uint32_t c0, uint32_t c1, int* local_flag)
 {
     const uint32_t L = (uint32_t)R.L;
@@ -147,6 +148,7 @@ __device__ void perc_chunk(const SwRep& R, uint32_t c0, uint32_t c1, int* local_
     const uint32_t nslots = (R.dim == 3) ? L * L : L;
     const uint32_t tailbits = L & 31u;
     const uint32_t tailmask = tailbits ? ((1u << tailbits) - 1u) : 0xFFFFFFFFu;
+    const bool open = (R.flags & FLAG_OPEN) != 0;
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int a = 0; a < R.dim; ++a) {
         for (uint32_t c = c0 + wave; c < c1; c += nw) {   // wave-uniform
@@ -154,7 +156,8 @@ __device__ void perc_chunk(const SwRep& R, uint32_t c0, uint32_t c1, int* local_
             bool gap = false;                            // a coordinate of this lane's words is not covered
             for (uint32_t w = lane; w < bw; w += 64u) {
                 const uint32_t v = bm[w];
-                const uint32_t want = (w == bw - 1u) ? tailmask : 0xFFFFFFFFu;
+                const uint32_t want = open ? ((w == bw - 1u) ? (1u << ((L - 1u) & 31u)) : 0u)
+                                           : ((w == bw - 1u) ? tailmask : 0xFFFFFFFFu);
                 gap = gap || (v & want) != want;
                 if (v) bm[w] = 0;
             }
@@ -213,15 +216,17 @@ __device__ void measure_range(const SwRep& R, uint32_t i0, uint32_t i1, uint32_t
     const uint32_t L = (uint32_t)R.L;
     const uint32_t LL = L * L;
     auto sp = [&](uint32_t j) { return 2 * (int)spin_up(R, j) - 1; };
+    const bool open = (R.flags & FLAG_OPEN) != 0;     // no link wraps around the box
     for (uint32_t i = i0; i < i1; i += stride) {
         const int sv = sp(i);
         const uint32_t x = i % L;
         const uint32_t y = (i / L) % L;
-        int nb = sp((x == L - 1) ? i - (L - 1) : i + 1);
-        nb += sp((y == L - 1) ? i - (L - 1) * L : i + L);
+        int nb = 0;
+        if (!(open && x == L - 1)) nb += sp((x == L - 1) ? i - (L - 1) : i + 1);
+        if (!(open && y == L - 1)) nb += sp((y == L - 1) ? i - (L - 1) * L : i + L);
         if (R.dim == 3) {
             const uint32_t z = i / LL;
-            nb += sp((z == L - 1) ? i - (L - 1) * LL : i + LL);
+            if (!(open && z == L - 1)) nb += sp((z == L - 1) ? i - (L - 1) * LL : i + LL);
         }
         m += sv;
         e += sv * nb;

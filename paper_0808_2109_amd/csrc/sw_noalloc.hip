@@ -126,7 +126,7 @@ extern "C" int sw_sweep_noalloc(const sw_params* params, int8_t* dev_spins, uint
     h.spins = dev_spins;
     h.lab32 = dev_labels;
     h.err = dev_err;
-    h.flags = dev_labels ? FLAG_KEEP : 0u;
+    h.flags = (dev_labels ? FLAG_KEEP : 0u) | ((params->flags & SW_OPEN) ? FLAG_OPEN : 0u);
     h.seed = params->seed;
     h.p = (params->p_bond < 0.0) ? -std::expm1(-2.0 * params->J / params->T) : params->p_bond;
     h.thr = threshold_from_p(h.p);

@@ -93,7 +93,7 @@ int validate_params(const sw_params* p)
     } else if (!(p->p_bond <= 1.0)) {
         return fail(SW_EINVAL, "p_bond must be in [0,1] or negative");
     }
-    if (p->flags & ~(uint32_t)(SW_RECORD_SERIES | SW_KEEP_LABELS | SW_PCC | SW_BITPACK))
+    if (p->flags & ~(uint32_t)(SW_RECORD_SERIES | SW_KEEP_LABELS | SW_PCC | SW_BITPACK | SW_OPEN))
         return fail(SW_EINVAL, "unknown flags");
     if (p->flags & SW_PCC) {
         if (!(p->pcc_dp0 > 0.0) || !std::isfinite(p->pcc_dp0)) return fail(SW_EINVAL, "pcc_dp0 must be > 0");
@@ -259,6 +259,7 @@ int replica_alloc(ReplicaH& r, const sw_params* p, int shape, hipStream_t stream
     if (p->flags & SW_KEEP_LABELS) h.flags |= FLAG_KEEP;
     if (p->flags & SW_PCC) h.flags |= FLAG_PCC;
     if (p->flags & SW_BITPACK) h.flags |= FLAG_BITPACK;
+    if (p->flags & SW_OPEN) h.flags |= FLAG_OPEN;
     h.seed = p->seed;
     h.p = (p->p_bond < 0.0) ? -std::expm1(-2.0 * p->J / p->T) : p->p_bond;
     h.thr = threshold_from_p(h.p);
