@@ -72,13 +72,18 @@ enum {
                                    i up iff bit i%32 of word i/32 is set.  Every
                                    result is the same as with int8 spins; sw_get_spins
                                    and sw_set_spins still take int8 arrays. */
-    SW_OPEN = 1u << 4           /* open boundaries in every axis (Sec. III discusses
+    SW_OPEN = 1u << 4,          /* open boundaries in every axis (Sec. III discusses
                                    both kinds): the links that would wrap around the
                                    box do not exist (every other link keeps its index
                                    and draw), E_int sums over the box's links, and the
                                    PCC test is the open box's spanning test: one
                                    cluster holds sites of both opposite faces
                                    (coordinate 0 and L-1) of some axis. */
+    SW_PCC_WIND = 1u << 5       /* with SW_PCC on a periodic box: percolation by the
+                                   topological rule of Sec. III (one cluster winds
+                                   around the box along some axis) instead of the
+                                   extension rule; SW_EINVAL without SW_PCC or with
+                                   SW_OPEN */
 };
 
 /* execution modes of a multi-replica handle (sw_set_mode) */
@@ -96,7 +101,7 @@ enum {
  *   p_bond          < 0: P = 1 - exp(-2J/T) (evaluated as -expm1(-2J/T) in double);
  *                   in [0,1]: use this P directly (the PCC start value)
  *   seed            key of the random stream
- *   flags           SW_RECORD_SERIES | SW_KEEP_LABELS | SW_PCC | SW_BITPACK | SW_OPEN
+ *   flags           SW_RECORD_SERIES | SW_KEEP_LABELS | SW_PCC | SW_BITPACK | SW_OPEN | SW_PCC_WIND
  *   pcc_dp0         PCC step dp at sweep 0 (> 0)
  *   pcc_halve_every dp is halved every this many sweeps (> 0)
  *   series_cap      capacity of the (E_int, M) series in sweeps (0: grows on demand)

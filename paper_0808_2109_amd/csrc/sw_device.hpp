@@ -38,7 +38,7 @@ constexpr int kBlock = 256;            // threads per workgroup (4 wave64)
 constexpr int kK3Block = SW_K3_THREADS;  // threads per K3 workgroup
 constexpr uint32_t kTagInit = 0, kTagBond = 1, kTagRefine = 2, kTagFlip = 3;
 
-enum : uint32_t { FLAG_SERIES = 1u, FLAG_KEEP = 2u, FLAG_PCC = 4u, FLAG_BITPACK = 8u, FLAG_OPEN = 16u };
+enum : uint32_t { FLAG_SERIES = 1u, FLAG_KEEP = 2u, FLAG_PCC = 4u, FLAG_BITPACK = 8u, FLAG_OPEN = 16u, FLAG_WIND = 32u };
 
 // --------------------------------------------------------------------------
 // Replica descriptor (device resident; the host keeps a mirror).
@@ -70,6 +70,8 @@ struct SwRep {
                                 // site i up iff bit i%32 of word i/32 is set
     uint16_t* lab16;            // N tile-local labels (tile-local index of the cluster's tile root)
     int32_t* par;               // N global union-find parents (border roots only)
+    uint64_t* par64;            // FLAG_WIND: N entries (parent | sheet offsets << 32) of the border
+                                // merge's union-find, which then replaces par until K3a
     int32_t* lab32;             // N final labels (FLAG_KEEP or FLAG_PCC), else null
     uint32_t* xbits;            // ntiles * xwords crossing-link bits
     uint32_t* fbits;            // ntiles * fbw: border roots of each tile (bit per tile-local site)
@@ -89,7 +91,7 @@ struct SwRep {
 
 // consistency checks on data-dependent indices: a violation sets a bit that
 // the host turns into an error instead of letting the access go out of range
-enum : int { ERR_TILE_LABEL = 1, ERR_PARENT = 2, ERR_SLOT = 3 };
+enum : int { ERR_TILE_LABEL = 1, ERR_PARENT = 2, ERR_SLOT = 3, ERR_WIND_RANGE = 4 };
 
 __device__ __forceinline__ void flag_error(const SwRep& R, int code)
 {
@@ -305,17 +307,24 @@ __device__ __forceinline__ void g_unite(const SwRep& R, int* par, int a, int b)
     }
 }
 
+// the parent of x in the border merge's union-find (the 64-bit entries of the
+// winding mode hold it in their low word)
+__device__ __forceinline__ int gpar(const SwRep& R, uint32_t x)
+{
+    return (R.flags & FLAG_WIND) ? (int)(uint32_t)R.par64[x] : R.par[x];
+}
+
 // read-only find, for phases that run after all unions are complete
 __device__ __forceinline__ uint32_t ro_find(const SwRep& R, uint32_t x)
 {
-    int p = R.par[x];
+    int p = gpar(R, x);
     while ((uint32_t)p != x) {
         if (p < 0 || (uint32_t)p > x) {
             flag_error(R, ERR_PARENT);
             return x;
         }
         x = (uint32_t)p;
-        p = R.par[x];
+        p = gpar(R, x);
     }
     return x;
 }
@@ -324,7 +333,7 @@ __device__ __forceinline__ uint32_t ro_find(const SwRep& R, uint32_t x)
 // step of the longer one)
 __device__ __forceinline__ void ro_find2(const SwRep& R, uint32_t& a, uint32_t& b)
 {
-    int pa = R.par[a], pb = R.par[b];
+    int pa = gpar(R, a), pb = gpar(R, b);
     while ((uint32_t)pa != a || (uint32_t)pb != b) {
         if (pa < 0 || (uint32_t)pa > a || pb < 0 || (uint32_t)pb > b) {
             flag_error(R, ERR_PARENT);
@@ -332,8 +341,113 @@ __device__ __forceinline__ void ro_find2(const SwRep& R, uint32_t& a, uint32_t& 
         }
         a = (uint32_t)pa;
         b = (uint32_t)pb;
-        pa = R.par[a];
-        pb = R.par[b];
+        pa = gpar(R, a);
+        pb = gpar(R, b);
+    }
+}
+
+// --------------------------------------------------------------------------
+// Union-find with sheet offsets, for the topological rule of Sec. III (a
+// cluster winds around the periodic box).  Every site of a tile-local
+// cluster lies on one sheet of the box's unwrapped cover (no link inside a
+// tile wraps), so a border root carries its cluster's sheet.  An entry holds
+// the parent in its low word and, above it, the sheet of the node minus the
+// sheet of its parent as three signed bytes (x, y, z).  A link that leaves
+// the box's last tile along axis d wraps: it moves one sheet along d.  A link
+// between two sites already in one set whose sheets disagree with the link
+// closes a loop around the box: the cluster winds.  Hooks (larger root under
+// the smaller, as in g_unite) are compare-and-swaps of a root's whole entry;
+// path halving stores composed offsets, which stay valid because an entry
+// only ever relates a node to one of its ancestors.
+// --------------------------------------------------------------------------
+struct Sheet {
+    int v[3];
+};
+
+__device__ __forceinline__ uint64_t pack64(uint32_t parent, const Sheet& k)
+{
+    return (uint64_t)parent | ((uint64_t)(uint8_t)k.v[0] << 32) | ((uint64_t)(uint8_t)k.v[1] << 40) |
+           ((uint64_t)(uint8_t)k.v[2] << 48);
+}
+
+__device__ __forceinline__ Sheet sheet_of(uint64_t e)
+{
+    return Sheet{{(int)(int8_t)(e >> 32), (int)(int8_t)(e >> 40), (int)(int8_t)(e >> 48)}};
+}
+
+__device__ __forceinline__ Sheet sheet_add(const SwRep& R, const Sheet& a, const Sheet& b)
+{
+    Sheet c;
+    for (int d = 0; d < 3; ++d) {
+        c.v[d] = a.v[d] + b.v[d];
+        if (c.v[d] > 127 || c.v[d] < -127) {   // never near on a box of this size; reported, not wrapped
+            flag_error(R, ERR_WIND_RANGE);
+            c.v[d] = 0;
+        }
+    }
+    return c;
+}
+
+__device__ __forceinline__ uint64_t g_load64(const uint64_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// root of x and the sheet of x minus the sheet of the root (-1: broken entry)
+__device__ __forceinline__ int g_find64(const SwRep& R, uint32_t x, Sheet& k)
+{
+    k = Sheet{{0, 0, 0}};
+    uint64_t* par = R.par64;
+    while (true) {
+        const uint64_t e = g_load64(&par[x]);
+        const uint32_t p = (uint32_t)e;
+        if (p == x) return (int)x;
+        if (p > x) {
+            flag_error(R, ERR_PARENT);
+            return -1;
+        }
+        const uint64_t f = g_load64(&par[p]);
+        const uint32_t gp = (uint32_t)f;
+        if (gp == p) {
+            k = sheet_add(R, k, sheet_of(e));
+            return (int)p;
+        }
+        if (gp > p) {
+            flag_error(R, ERR_PARENT);
+            return -1;
+        }
+        const Sheet kx = sheet_add(R, sheet_of(e), sheet_of(f));   // x relative to its grandparent
+        __hip_atomic_store(&par[x], pack64(gp, kx), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        k = sheet_add(R, k, kx);
+        x = gp;
+    }
+}
+
+// union of a and b across a link that moves w sheets (sheet(b) = sheet(a) + w);
+// sets the replica's percolation flag when the link closes a loop around the box
+__device__ __forceinline__ void g_unite64(const SwRep& R, uint32_t a, uint32_t b, const Sheet& w)
+{
+    while (true) {
+        Sheet ka, kb;
+        const int ra = g_find64(R, a, ka), rb = g_find64(R, b, kb);
+        if (ra < 0 || rb < 0) return;
+        Sheet d;   // sheet(rb) - sheet(ra)
+        for (int c = 0; c < 3; ++c) d.v[c] = w.v[c] - kb.v[c] + ka.v[c];
+        if (ra == rb) {
+            if (d.v[0] | d.v[1] | d.v[2]) atomicOr(R.pflag, 1);
+            return;
+        }
+        uint32_t lo = (uint32_t)ra, hi = (uint32_t)rb;
+        if (ra > rb) {
+            lo = (uint32_t)rb;
+            hi = (uint32_t)ra;
+            for (int c = 0; c < 3; ++c) d.v[c] = -d.v[c];
+        }
+        uint64_t expect = pack64(hi, Sheet{{0, 0, 0}});
+        if (__hip_atomic_compare_exchange_strong(&R.par64[hi], &expect, pack64(lo, d), __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            return;
+        // hi was hooked meanwhile: start again from the two sites
     }
 }
 
@@ -870,7 +984,7 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
     //    consecutive runs of one cluster before the LDS atomics.
     // (a batched launch runs this variant for every replica of a batch that
     // holds a PCC replica: only PCC replicas have coverage entries)
-    if constexpr (PCC) if (R.flags & FLAG_PCC) {
+    if constexpr (PCC) if ((R.flags & (FLAG_PCC | FLAG_WIND)) == FLAG_PCC) {
         using CV = K1Cov<C, true>;
         constexpr int WPL = (C::FBW + 63) / 64;         // bitmap words per lane of wave 0
         if (tid < 64) {
@@ -949,7 +1063,8 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
             const int b = __ffs(m) - 1;
             m &= m - 1u;
             const uint32_t gi = local_to_global<C>((uint32_t)(hw * 16 + b), g.x0, g.y0, g.z0, (int)L);
-            R.par[gi] = (int32_t)gi;
+            if (R.flags & FLAG_WIND) R.par64[gi] = (uint64_t)gi;   // own root, sheet offset 0
+            else R.par[gi] = (int32_t)gi;
         }
     }
     if (tid < C::W0) R.xbits[(size_t)t * C::XW + tid] = sm.XF[tid];
@@ -1095,7 +1210,15 @@ __device__ void k2_tile(const SwRep& R, int t, K2Smem<C>& sm)
             flag_error(R, ERR_TILE_LABEL);
             continue;
         }
-        g_unite(R, R.par, (int)ra, (int)rb);
+        if (R.flags & FLAG_WIND) {
+            // the link leaves the box's last tile along d: it wraps
+            const bool wraps = (d == 0) ? ix + 1 == R.ntx : (d == 1) ? iy + 1 == R.nty : iz + 1 == R.ntz;
+            Sheet w{{0, 0, 0}};
+            if (wraps) w.v[d] = 1;
+            g_unite64(R, ra, rb, w);
+        } else {
+            g_unite(R, R.par, (int)ra, (int)rb);
+        }
     }
     __syncthreads();
 }
@@ -1229,7 +1352,7 @@ __device__ void k3a_tile(const SwRep& R, int t, uint32_t s, K3aSmem<C>& sm, CovA
     const TileGeo g = tile_geo<C>(R, t);
     const uint32_t k0 = (uint32_t)R.seed, k1 = (uint32_t)(R.seed >> 32);
     const bool keep = R.lab32 != nullptr;
-    const bool pcc = (R.flags & FLAG_PCC) != 0;
+    const bool pcc = (R.flags & (FLAG_PCC | FLAG_WIND)) == FLAG_PCC;   // extension rule or open-box spanning
     static_assert(C::NR == 64, "one tile row per lane");
     // the border roots in bitmap order (rank order, the order of K1's
     // coverage entries): lane l takes words [l * WPL, (l + 1) * WPL)
@@ -1292,7 +1415,9 @@ __device__ void k3a_tile(const SwRep& R, int t, uint32_t s, K3aSmem<C>& sm, CovA
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             if (e == 1 && !two) break;
-            if (keep && root[e] != gi[e]) R.par[gi[e]] = (int32_t)root[e];
+            // (in winding mode K1 set up only the 64-bit entries, so a root
+            // that is its own cluster's root is written too)
+            if (keep && (root[e] != gi[e] || (R.flags & FLAG_WIND))) R.par[gi[e]] = (int32_t)root[e];
             if (flip_bit(root[e], s, k0, k1)) atomicOr(&sm.BF[lr[e] >> 5], 1u << (lr[e] & 31u));
             sm.root[i + 64 * e] = root[e];
         }

@@ -385,7 +385,7 @@ __global__ __launch_bounds__(kBlock) void kbc_kernel(SwRep* reps, const EngineIt
     if (i >= nitems) return;
     const SwRep R = reps[items[i].rep];
     uint32_t s;
-    if (!(R.flags & FLAG_PCC) || !rep_runs(R, it, n_sweeps, s)) return;
+    if ((R.flags & (FLAG_PCC | FLAG_WIND)) != FLAG_PCC || !rep_runs(R, it, n_sweeps, s)) return;
     if (R.dim == 2) k_cand_tile<C2>(R, items[i].tile, s);
     else k_cand_tile<C3>(R, items[i].tile, s);
 }
@@ -436,7 +436,7 @@ __global__ __launch_bounds__(kBlock) void kbp_kernel(SwRep* reps, const EngineIt
     if (i >= nitems) return;
     const SwRep R = reps[items[i].rep];
     uint32_t s;
-    if (!(R.flags & FLAG_PCC) || !rep_runs(R, it, n_sweeps, s)) return;
+    if ((R.flags & (FLAG_PCC | FLAG_WIND)) != FLAG_PCC || !rep_runs(R, it, n_sweeps, s)) return;
     const uint32_t nslots = (R.dim == 3) ? (uint32_t)R.L * (uint32_t)R.L : (uint32_t)R.L;
     const uint32_t c0 = min(nslots, (uint32_t)items[i].tile * (uint32_t)kPercChunk);
     const uint32_t c1 = min(nslots, c0 + (uint32_t)kPercChunk);
@@ -601,8 +601,14 @@ int launch_cand(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream)
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
+// the percolation test (coverage bitmaps; the border merge itself flags a
+// winding cluster) and the feedback step
 int launch_perc(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream)
 {
+    if (h.flags & FLAG_WIND) {
+        hipLaunchKernelGGL(kpcc_update_kernel, dim3(1), dim3(64), 0, stream, d, s);
+        return hipGetLastError() == hipSuccess ? 0 : -3;
+    }
     const uint32_t nslots = (h.dim == 3) ? (uint32_t)h.L * (uint32_t)h.L : (uint32_t)h.L;
     int grid = (int)((nslots + kBlock - 1) / kBlock);
     if (grid > 2048) grid = 2048;

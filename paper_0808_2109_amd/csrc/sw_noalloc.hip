@@ -97,7 +97,7 @@ extern "C" int sw_sweep_noalloc(const sw_params* params, int8_t* dev_spins, uint
 {
     int rc = validate_params(params);
     if (rc) return rc;
-    if (params->flags & SW_PCC) return fail(SW_EINVAL, "the allocation-free sweep has no PCC feedback");
+    if (params->flags & (SW_PCC | SW_PCC_WIND)) return fail(SW_EINVAL, "the allocation-free sweep has no PCC feedback");
     if (params->flags & SW_BITPACK) return fail(SW_EINVAL, "the allocation-free sweep takes int8 spins");
     if (!dev_spins) return fail(SW_EINVAL, "null spin array");
     if (n_sweeps < 0) return fail(SW_EINVAL, "negative sweep count");

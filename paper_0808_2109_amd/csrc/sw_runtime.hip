@@ -93,8 +93,10 @@ int validate_params(const sw_params* p)
     } else if (!(p->p_bond <= 1.0)) {
         return fail(SW_EINVAL, "p_bond must be in [0,1] or negative");
     }
-    if (p->flags & ~(uint32_t)(SW_RECORD_SERIES | SW_KEEP_LABELS | SW_PCC | SW_BITPACK | SW_OPEN))
+    if (p->flags & ~(uint32_t)(SW_RECORD_SERIES | SW_KEEP_LABELS | SW_PCC | SW_BITPACK | SW_OPEN | SW_PCC_WIND))
         return fail(SW_EINVAL, "unknown flags");
+    if ((p->flags & SW_PCC_WIND) && (!(p->flags & SW_PCC) || (p->flags & SW_OPEN)))
+        return fail(SW_EINVAL, "the topological rule needs SW_PCC on a periodic box");
     if (p->flags & SW_PCC) {
         if (!(p->pcc_dp0 > 0.0) || !std::isfinite(p->pcc_dp0)) return fail(SW_EINVAL, "pcc_dp0 must be > 0");
         if (p->pcc_halve_every == 0) return fail(SW_EINVAL, "pcc_halve_every must be > 0");
@@ -155,6 +157,7 @@ uint64_t footprint_bytes(const sw_params* p, int shape)
     uint64_t b = n * (2 + 4);                                // lab16, par
     b += (p->flags & SW_BITPACK) ? (n + 31) / 32 * 4 : n;    // spins
     if (p->flags & SW_KEEP_LABELS) b += 4 * n;               // lab32
+    if (p->flags & SW_PCC_WIND) b += 8 * n;                  // parents with sheet offsets
     b += tile_bytes(h, (p->flags & SW_PCC) != 0);            // crossing bits, bitmaps, face labels, coverage
     b += 64;                                                 // accumulators
     if (p->flags & SW_PCC) {
@@ -221,6 +224,7 @@ void replica_free(ReplicaH& r)
     if (r.own_spins) dfree(r.h.spins);
     dfree(r.h.lab16);
     dfree(r.h.par);
+    dfree(r.h.par64);
     dfree(r.h.lab32);
     dfree(r.h.xbits);
     dfree(r.h.fbits);
@@ -237,6 +241,7 @@ void replica_free(ReplicaH& r)
     r.h.spins = nullptr;
     r.h.lab16 = nullptr;
     r.h.par = r.h.lab32 = r.h.pflag = r.h.perc_trace = nullptr;
+    r.h.par64 = nullptr;
     r.h.xbits = r.h.fbits = r.h.bflip = r.h.bmp = nullptr;
     r.h.face = nullptr;
     r.h.series = r.h.acc = nullptr;
@@ -260,6 +265,7 @@ int replica_alloc(ReplicaH& r, const sw_params* p, int shape, hipStream_t stream
     if (p->flags & SW_PCC) h.flags |= FLAG_PCC;
     if (p->flags & SW_BITPACK) h.flags |= FLAG_BITPACK;
     if (p->flags & SW_OPEN) h.flags |= FLAG_OPEN;
+    if (p->flags & SW_PCC_WIND) h.flags |= FLAG_WIND;
     h.seed = p->seed;
     h.p = (p->p_bond < 0.0) ? -std::expm1(-2.0 * p->J / p->T) : p->p_bond;
     h.thr = threshold_from_p(h.p);
@@ -275,6 +281,8 @@ int replica_alloc(ReplicaH& r, const sw_params* p, int shape, hipStream_t stream
     if ((rc = dmalloc((void**)&h.spins, spin_bytes(h), "spins"))) goto bad;
     if ((rc = dmalloc((void**)&h.lab16, 2 * n, "tile labels"))) goto bad;
     if ((rc = dmalloc((void**)&h.par, 4 * n, "union-find parents"))) goto bad;
+    if (h.flags & FLAG_WIND)
+        if ((rc = dmalloc((void**)&h.par64, 8 * n, "union-find parents with sheet offsets"))) goto bad;
     if (h.flags & FLAG_KEEP)
         if ((rc = dmalloc((void**)&h.lab32, 4 * n, "labels"))) goto bad;
     if ((rc = alloc_tile_buffers(h))) goto bad;
@@ -542,7 +550,7 @@ int plain_sweep(sw_lattice* h, int r, int32_t n)
         }
         TIMED(h, 0, launch_k1(m, d, s, em, h->stream, h->per_cu[0]));
         TIMED(h, 1, launch_k2(m, d, h->stream));
-        if (pcc) TIMED(h, 3, launch_cand(m, d, s, h->stream));
+        if (pcc && !(m.flags & FLAG_WIND)) TIMED(h, 3, launch_cand(m, d, s, h->stream));
         TIMED(h, 6, launch_k3a(m, d, s, h->stream));
         TIMED(h, 2, launch_k3(m, d, s, h->stream, h->per_cu[2]));
         if (pcc) TIMED(h, 3, launch_perc(m, d, s, h->stream));
@@ -572,10 +580,10 @@ static int build_items(sw_lattice* h)
         for (int t = 0; t < m.ntiles; ++t) {
             items.push_back(EngineItem{(int32_t)r, t});
             const int ix = t % m.ntx, iy = (t / m.ntx) % m.nty, iz = t / (m.ntx * m.nty);
-            if ((m.flags & FLAG_PCC) && (ix == 0 || iy == 0 || (m.dim == 3 && iz == 0)))
+            if ((m.flags & (FLAG_PCC | FLAG_WIND)) == FLAG_PCC && (ix == 0 || iy == 0 || (m.dim == 3 && iz == 0)))
                 cand.push_back(EngineItem{(int32_t)r, t});
         }
-        if (m.flags & FLAG_PCC) {
+        if ((m.flags & (FLAG_PCC | FLAG_WIND)) == FLAG_PCC) {
             const int64_t nslots = (m.dim == 3) ? (int64_t)m.L * m.L : (int64_t)m.L;
             for (int64_t k = 0; k * kPercChunk < nslots; ++k) perc.push_back(EngineItem{(int32_t)r, (int32_t)k});
         }

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libswgpu.so")
 
 SW_OK, SW_EINVAL, SW_ENOMEM, SW_EHIP, SW_EBUSY, SW_ENOTFOUND, SW_ECANCELLED, SW_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
-SW_RECORD_SERIES, SW_KEEP_LABELS, SW_PCC, SW_BITPACK, SW_OPEN = 1, 2, 4, 8, 16
+SW_RECORD_SERIES, SW_KEEP_LABELS, SW_PCC, SW_BITPACK, SW_OPEN, SW_PCC_WIND = 1, 2, 4, 8, 16, 32
 SW_MODE_PLAIN, SW_MODE_BATCHED = 0, 1
 JOB_STATES = {0: "queued", 1: "running", 2: "done", 3: "rejected", 4: "cancelled"}
 PHASES = ("k1_bond_label", "k2_merge", "k3_flip", "pcc", "measure", "batched", "k3_resolve")
@@ -137,7 +137,7 @@ def default_stream():
 def make_params(dim: int = 2, L: int = 64, T: Optional[float] = None, seed: int = 1, J: float = 1.0,
                 p_bond: float = -1.0, series: bool = False, keep_labels: bool = False, pcc: bool = False,
                 dp0: float = 0.01, halve_every: int = 1000, series_cap: int = 0, bitpack: bool = False,
-                open_bc: bool = False) -> sw_params:
+                open_bc: bool = False, wind: bool = False) -> sw_params:
     p = sw_params()
     lib().sw_params_default(ctypes.byref(p))
     p.dim, p.L, p.J, p.seed = dim, L, J, seed
@@ -145,7 +145,7 @@ def make_params(dim: int = 2, L: int = 64, T: Optional[float] = None, seed: int 
         p.T = T
     p.p_bond = p_bond
     p.flags = ((SW_RECORD_SERIES if series else 0) | (SW_KEEP_LABELS if keep_labels else 0) | (SW_PCC if pcc else 0)
-               | (SW_BITPACK if bitpack else 0) | (SW_OPEN if open_bc else 0))
+               | (SW_BITPACK if bitpack else 0) | (SW_OPEN if open_bc else 0) | (SW_PCC_WIND if wind else 0))
     p.pcc_dp0, p.pcc_halve_every, p.series_cap = dp0, halve_every, series_cap
     return p
 
