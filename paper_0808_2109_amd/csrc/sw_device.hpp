@@ -608,10 +608,20 @@ __device__ __forceinline__ uint32_t packed_bits(const uint32_t* w, uint32_t pos,
     return n >= 32 ? v : v & ((1u << n) - 1u);
 }
 
-// up bits of the n <= 16 sites from site index i, int8 or bit-packed
+// up bits of the n <= 16 sites from site index i, int8 or bit-packed.  A
+// full part that does not start on a 16-byte boundary is read as the five
+// aligned words around it, cut with byte alignment, when those words lie
+// inside the array.
 __device__ __forceinline__ uint32_t load_spins(const SwRep& R, uint32_t i, int n, bool wide)
 {
     if (R.flags & FLAG_BITPACK) return packed_bits(reinterpret_cast<const uint32_t*>(R.spins), i, n);
+    if (!wide && n == 16 && (i & ~3u) + 20u <= R.N) {
+        const uint32_t* w = reinterpret_cast<const uint32_t*>(R.spins + (i & ~3u));
+        const uint32_t sh = i & 3u;
+        const uint32_t d0 = w[0], d1 = w[1], d2 = w[2], d3 = w[3], d4 = w[4];
+        return up16(make_uint4(__builtin_amdgcn_alignbyte(d1, d0, sh), __builtin_amdgcn_alignbyte(d2, d1, sh),
+                               __builtin_amdgcn_alignbyte(d3, d2, sh), __builtin_amdgcn_alignbyte(d4, d3, sh)));
+    }
     return load_part(R.spins + i, n, wide);
 }
 
@@ -661,11 +671,14 @@ __device__ inline uint32_t part_bonds(uint32_t eq, uint32_t lbase, int n, uint32
     return op;
 }
 
-// First stage of part_bonds for an aligned part: the bonds that the high
+// First stage of part_bonds for a part of 16 links: the bonds that the high
 // bytes decide, and in `ties` the equal links whose byte equals thr >> 24
 // (decided by the REFINE stream; the caller draws those for all directions
 // in one loop, so a wave pays about one refinement call per sweep instead of
-// one per direction)
+// one per direction).  When the part does not start on a 16-link boundary
+// (L not a multiple of 16) its 16 bytes are bytes o..15 of one BOND block and
+// 0..o-1 of the next, o = lbase mod 16: both blocks are drawn and the window
+// is cut out of their eight words.
 __device__ __forceinline__ uint32_t part_bonds_coarse(uint32_t eq, uint32_t lbase, uint32_t s, uint32_t t_hi,
                                                       uint32_t k0, uint32_t k1, uint32_t& ties)
 {
@@ -673,7 +686,18 @@ __device__ __forceinline__ uint32_t part_bonds_coarse(uint32_t eq, uint32_t lbas
     if (!eq) return 0;
     if (t_hi >= 256u) return eq;                     // P = 1: every equal link is a bond
     const uint32_t y4 = t_hi * 0x01010101u;
-    const U4 q = philox10(lbase >> 4, 0u, s, kTagBond, k0, k1);
+    U4 q = philox10(lbase >> 4, 0u, s, kTagBond, k0, k1);
+    const uint32_t o = lbase & 15u;
+    if (o) {
+        const U4 n = philox10((lbase >> 4) + 1u, 0u, s, kTagBond, k0, k1);
+        const uint32_t w[8] = {q.x, q.y, q.z, q.w, n.x, n.y, n.z, n.w};
+        const uint32_t j = o >> 2, sh = o & 3u;   // first word, byte offset within it
+        uint32_t v[5];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) v[i] = (j == 0) ? w[i] : (j == 1) ? w[i + 1] : (j == 2) ? w[i + 2] : w[i + 3];
+        q = U4{__builtin_amdgcn_alignbyte(v[1], v[0], sh), __builtin_amdgcn_alignbyte(v[2], v[1], sh),
+               __builtin_amdgcn_alignbyte(v[3], v[2], sh), __builtin_amdgcn_alignbyte(v[4], v[3], sh)};
+    }
     const uint32_t bits = nibbles4(bytes_lt(q.x, y4), bytes_lt(q.y, y4), bytes_lt(q.z, y4), bytes_lt(q.w, y4)) & eq;
     if (has_zero_byte(q.x ^ y4) | has_zero_byte(q.y ^ y4) | has_zero_byte(q.z ^ y4) | has_zero_byte(q.w ^ y4))
         ties = nibbles4(bytes_eq(q.x, y4), bytes_eq(q.y, y4), bytes_eq(q.z, y4), bytes_eq(q.w, y4)) & eq;
@@ -767,7 +791,7 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
         for (int d = 0; d < C::D; ++d) {
             const uint32_t eqp = (uint32_t)(eq[d] >> xp) & 0xFFFFu;
             const uint32_t lbase = (uint32_t)d * N + gi0 + (uint32_t)xp;
-            if (partok && wide) {
+            if (partok && np == 16) {
                 uint32_t td;
                 bits[d] = part_bonds_coarse(eqp, lbase, s, t_hi, k0, k1, td);
                 ties |= (uint64_t)td << (16 * d);
@@ -1660,13 +1684,24 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
             *reinterpret_cast<uint32_t*>(R.spins + gi) = out;
         }
     } else {
-        for (int k0 = 0; k0 < C::TS; k0 += kK3Block) {
-            const int k = k0 + tid;
-            const int xk = k % C::TX, r = k / C::TX;
+        // rows that are not whole quads of sites: each thread takes four
+        // consecutive sites of a row (the index arithmetic once per group),
+        // with per-site loads and stores
+#pragma unroll
+        for (int j = 0; j < QPT; ++j) {
+            const int qd = tid + kK3Block * j;
+            const int r = qd / QR, xq = (qd % QR) * 4;
             const int ly = r % C::TY, lz = r / C::TY;
-            const bool valid = ly < g.wy && lz < g.wz && xk < g.wx;
-            const uint32_t gi = (uint32_t)(g.x0 + xk) + L * ((uint32_t)(g.y0 + ly) + L * (uint32_t)(g.z0 + lz));
-            if (valid) R.spins[gi] = (int8_t)k3_site<C>(R, sm, g, R.lab16[gi], k, gi, labels);
+            if (!(ly < g.wy && lz < g.wz && xq < g.wx)) continue;
+            const uint32_t gi = (uint32_t)(g.x0 + xq) + L * ((uint32_t)(g.y0 + ly) + L * (uint32_t)(g.z0 + lz));
+            const int k = r * C::TX + xq;
+            const int nq = min(4, g.wx - xq);
+            uint16_t lab[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) lab[i] = (i < nq) ? R.lab16[gi + (uint32_t)i] : 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (i < nq) R.spins[gi + (uint32_t)i] = (int8_t)k3_site<C>(R, sm, g, lab[i], k + i, gi + (uint32_t)i, labels);
         }
     }
     __syncthreads();
