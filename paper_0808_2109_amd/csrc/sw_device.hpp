@@ -952,21 +952,38 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
                 rt[4 * k + 3] = v.w;
             }
         }
+        // border runs of the row as a mask of their run starts: every run of
+        // a near row, the run at x = 0, the last run when its x-link leaves
+        // the tile, and every run holding a link that leaves through a far y
+        // / z face.  A run [s, e] holds a bit of `cross` when, in the
+        // bit-reversed row (where the run is [63-e, 63-s] with its start on
+        // top), a carry started at a reversed cross bit climbs to the top
+        // through positions that are not a run's bottom (an end, reversed).
+        uint64_t bs;
+        if (nearrow) {
+            bs = SS;
+        } else {
+            bs = 1ull | (xout ? (1ull << last) : 0ull);
+            if (cross) {
+                const uint64_t ends = ((SS >> 1) | (1ull << (g.wx - 1))) & lbw;
+                const uint64_t y = __builtin_bitreverse64(cross & lbw);
+                const uint64_t cont = ~__builtin_bitreverse64(ends);
+                const uint64_t a = y | cont;
+                const uint64_t carry = (a + y) ^ a ^ y;
+                bs |= __builtin_bitreverse64(((carry & cont) | y) & __builtin_bitreverse64(SS));
+            }
+            bs &= SS;
+        }
+        for (uint32_t bm = (uint32_t)(bs >> xp) & ss16; bm; bm &= bm - 1u) {
+            const uint32_t root = (uint32_t)lds_load(&sm.par[rowk + xp + __builtin_ctz(bm)]);
+            atomicOr(&sm.FB[root >> 5], 1u << (root & 31u));
+        }
+        // the labels of the part: each site takes the root of its run
         uint32_t cur = (ss16 & 1u) ? rt[0] : (uint32_t)lds_load(&sm.par[rowk + start_at(SS, xp)]);
         uint32_t pk[8];
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-            if ((ss16 >> j) & 1u) {
-                const int x = xp + j;
-                cur = rt[j];
-                bool b = nearrow || x == 0 || (x == last && xout);
-                if (!b && cross) {
-                    const uint64_t later = SS & ~low_bits(x + 1);
-                    const int xe = later ? __builtin_ctzll(later) - 1 : g.wx - 1;   // last site of the run
-                    b = (cross & low_bits(xe + 1) & ~low_bits(x)) != 0ull;
-                }
-                if (b) atomicOr(&sm.FB[cur >> 5], 1u << (cur & 31u));
-            }
+            cur = ((ss16 >> j) & 1u) ? rt[j] : cur;
             if (j & 1) pk[j >> 1] |= cur << 16;
             else pk[j >> 1] = cur;
         }
