@@ -151,6 +151,16 @@ int sw_set_batch_grid(sw_lattice* h, int32_t per_cu);
 /* Current launch shape of batched sweeps (see sw_set_batch_grid). */
 int sw_get_batch_grid(sw_lattice* h, int32_t* per_cu);
 
+/* Merge schedule of the border merge (the global union across tile faces that
+ * reconciles the domains' labels, Sec. II): threads per tile, 64 (one wave per
+ * tile: more tiles in flight) or 256 (each thread fewer face sites); 0 picks
+ * per tile shape.  Results never depend on it; the autotuner sets it too.
+ * SW_EINVAL for other values. */
+int sw_set_merge_width(sw_lattice* h, int32_t threads);
+
+/* Current merge schedule (see sw_set_merge_width). */
+int sw_get_merge_width(sw_lattice* h, int32_t* threads);
+
 /*
  * Advance every replica by n_sweeps sweeps (Sec. I steps 1-3, plus the PCC
  * feedback of Sec. III for SW_PCC replicas).  Asynchronous on the stream.

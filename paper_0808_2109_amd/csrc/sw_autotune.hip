@@ -1,12 +1,15 @@
-// sw_autotune.hip -- tile-shape and batched-grid autotuner.
+// sw_autotune.hip -- tile-shape, merge-schedule and batched-grid autotuner.
 //
-// Results never depend on the tile shape or the grid (every union hooks to
-// the smaller root), so the tuner is free to pick whatever runs fastest.
-//   one replica:   every compiled tile shape is timed with plain launches on
-//                  a scratch lattice with the same parameters and state;
-//   many replicas: every batched variant (a 2D and a 3D shape) and three
-//                  grid sizes are timed on a scratch copy of all replicas
-//                  (parameters and state) in batched mode.
+// Results never depend on the tile shape, the border-merge width or the grid
+// (every union hooks to the smaller root), so the tuner is free to pick
+// whatever runs fastest.
+//   one replica:   every compiled tile shape, each with both border-merge
+//                  widths (64 and 256 threads per tile), is timed with plain
+//                  launches on a scratch lattice with the same parameters
+//                  and state;
+//   many replicas: every batched variant (a 2D and a 3D shape), both merge
+//                  widths and four grid sizes are timed on a scratch copy of
+//                  all replicas (parameters and state) in batched mode.
 // Choices are cached as JSON keyed by (arch, dim, size class = floor(log2 L))
 // for single lattices and by (arch, "batch", replica count, total sites) for
 // batches.
@@ -30,10 +33,17 @@ static int size_class(int L)
     return c;
 }
 
-// minimal reader for the cache this file writes: {"key": {"shape": s, "grid": g, ...}, ...}
-static std::map<std::string, std::pair<int, int>> read_cache(const char* path)
+struct Choice {
+    int shape, grid, merge;
+    double ms;
+};
+
+// minimal reader for the cache this file writes:
+// {"key": {"shape": s, "grid": g, "merge": m, ...}, ...}; an entry without
+// "merge" takes the default schedule (0)
+static std::map<std::string, Choice> read_cache(const char* path)
 {
-    std::map<std::string, std::pair<int, int>> out;
+    std::map<std::string, Choice> out;
     if (!path) return out;
     FILE* f = fopen(path, "rb");
     if (!f) return out;
@@ -47,34 +57,31 @@ static std::map<std::string, std::pair<int, int>> read_cache(const char* path)
         const size_t end = txt.find('"', pos + 1);
         if (end == std::string::npos) break;
         const std::string key = txt.substr(pos + 1, end - pos - 1);
+        const size_t close = txt.find('}', end);
         const size_t sp = txt.find("\"shape\":", end);
         const size_t gp = txt.find("\"grid\":", end);
-        if (sp == std::string::npos || gp == std::string::npos) break;
-        out[key] = {atoi(txt.c_str() + sp + 8), atoi(txt.c_str() + gp + 7)};
+        if (sp == std::string::npos || gp == std::string::npos || close == std::string::npos) break;
+        const size_t mp = txt.find("\"merge\":", end);
+        const int merge = (mp != std::string::npos && mp < close) ? atoi(txt.c_str() + mp + 8) : 0;
+        out[key] = Choice{atoi(txt.c_str() + sp + 8), atoi(txt.c_str() + gp + 7), merge, -1.0};
         pos = end + 1;
     }
     return out;
 }
 
-struct Choice {
-    int shape, grid;
-    double ms;
-};
-
 static void write_cache(const char* path, const std::map<std::string, Choice>& entries)
 {
     if (!path) return;
-    auto old = read_cache(path);
-    std::map<std::string, Choice> all;
-    for (auto& kv : old) all[kv.first] = Choice{kv.second.first, kv.second.second, -1.0};
+    std::map<std::string, Choice> all = read_cache(path);
     for (auto& kv : entries) all[kv.first] = kv.second;
     FILE* f = fopen(path, "wb");
     if (!f) return;
     fprintf(f, "{\n");
     size_t i = 0;
     for (auto& kv : all) {
-        fprintf(f, "  \"%s\": {\"shape\": %d, \"grid\": %d, \"ms_per_sweep\": %.6f}%s\n", kv.first.c_str(),
-                kv.second.shape, kv.second.grid, kv.second.ms, (++i < all.size()) ? "," : "");
+        fprintf(f, "  \"%s\": {\"shape\": %d, \"grid\": %d, \"merge\": %d, \"ms_per_sweep\": %.6f}%s\n",
+                kv.first.c_str(), kv.second.shape, kv.second.grid, kv.second.merge, kv.second.ms,
+                (++i < all.size()) ? "," : "");
     }
     fprintf(f, "}\n");
     fclose(f);
@@ -127,30 +134,38 @@ static int tune_single(sw_lattice* h, int32_t sweeps, const char* cache_path)
     snprintf(key, sizeof(key), "gfx950:d%d:l%d", rep.h.dim, size_class(rep.h.L));
     auto cached = read_cache(cache_path);
     auto it = cached.find(key);
-    if (it != cached.end() && it->second.first >= 0 && it->second.first < shape_count(rep.h.dim))
-        return sw_set_tile_shape(h, 0, it->second.first);
+    if (it != cached.end() && it->second.shape >= 0 && it->second.shape < shape_count(rep.h.dim)) {
+        int rc = sw_set_tile_shape(h, 0, it->second.shape);
+        return rc ? rc : sw_set_merge_width(h, it->second.merge);
+    }
     sw_params p = rep.prm;
     p.flags &= ~(uint32_t)SW_RECORD_SERIES;
-    int best = default_shape(p.dim);
+    int best = default_shape(p.dim), best_merge = 0;
     double best_ms = 1e30;
     for (int shape = 0; shape < shape_count(p.dim); ++shape) {
         sw_lattice* s = nullptr;
         int rc = sw_init(&p, 1, -1, h->stream, &s);
         if (!rc) rc = sw_set_tile_shape(s, 0, shape);
-        if (!rc) rc = copy_state(s, 0, h, 0);
-        double ms = 0;
-        if (!rc) rc = time_sweeps(s, sweeps, &ms);
+        for (int merge : {64, 256}) {
+            if (rc) break;
+            rc = copy_state(s, 0, h, 0);
+            if (!rc) rc = sw_set_merge_width(s, merge);
+            double ms = 0;
+            if (!rc) rc = time_sweeps(s, sweeps, &ms);
+            if (!rc && ms < best_ms) {
+                best_ms = ms;
+                best = shape;
+                best_merge = merge;
+            }
+        }
         if (s) sw_free(s);
         if (rc) return rc;
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = shape;
-        }
     }
     std::map<std::string, Choice> out;
-    out[key] = Choice{best, 0, best_ms};
+    out[key] = Choice{best, 0, best_merge, best_ms};
     write_cache(cache_path, out);
-    return sw_set_tile_shape(h, 0, best);
+    int rc = sw_set_tile_shape(h, 0, best);
+    return rc ? rc : sw_set_merge_width(h, best_merge);
 }
 
 static int tune_batch(sw_lattice* h, int32_t sweeps, const char* cache_path)
@@ -159,13 +174,14 @@ static int tune_batch(sw_lattice* h, int32_t sweeps, const char* cache_path)
     for (auto& r : h->reps) total += r.h.N;
     char key[96];
     snprintf(key, sizeof(key), "gfx950:batch:r%zu:n%llu", h->reps.size(), (unsigned long long)total);
-    int best_v = 0, best_grid = 0;
+    int best_v = 0, best_grid = 0, best_merge = 0;
     double best_ms = 1e30;
     auto cached = read_cache(cache_path);
     auto it = cached.find(key);
-    if (it != cached.end() && it->second.first >= 0 && it->second.first < shape_count(2)) {
-        best_v = it->second.first;
-        best_grid = it->second.second;
+    if (it != cached.end() && it->second.shape >= 0 && it->second.shape < shape_count(2)) {
+        best_v = it->second.shape;
+        best_grid = it->second.grid;
+        best_merge = it->second.merge;
     } else {
         std::vector<sw_params> ps;
         for (auto& r : h->reps) {
@@ -179,22 +195,26 @@ static int tune_batch(sw_lattice* h, int32_t sweeps, const char* cache_path)
             for (size_t r = 0; r < ps.size() && !rc; ++r) rc = sw_set_tile_shape(s, (int32_t)r, v);
             for (size_t r = 0; r < ps.size() && !rc; ++r) rc = copy_state(s, (int)r, h, (int)r);
             if (!rc) s->mode = SW_MODE_BATCHED;
-            for (int per_cu : {0, 4, 8, 16}) {
-                if (rc) break;
-                s->batch_per_cu = per_cu;
-                double ms = 0;
-                rc = time_sweeps(s, sweeps, &ms);
-                if (!rc && ms < best_ms) {
-                    best_ms = ms;
-                    best_v = v;
-                    best_grid = per_cu;
+            for (int merge : {64, 256}) {
+                for (int per_cu : {0, 4, 8, 16}) {
+                    if (rc) break;
+                    s->batch_per_cu = per_cu;
+                    s->merge_width = merge;
+                    double ms = 0;
+                    rc = time_sweeps(s, sweeps, &ms);
+                    if (!rc && ms < best_ms) {
+                        best_ms = ms;
+                        best_v = v;
+                        best_grid = per_cu;
+                        best_merge = merge;
+                    }
                 }
             }
             if (s) sw_free(s);
             if (rc) return rc;
         }
         std::map<std::string, Choice> out;
-        out[key] = Choice{best_v, best_grid, best_ms};
+        out[key] = Choice{best_v, best_grid, best_merge, best_ms};
         write_cache(cache_path, out);
     }
     for (size_t r = 0; r < h->reps.size(); ++r) {
@@ -202,7 +222,7 @@ static int tune_batch(sw_lattice* h, int32_t sweeps, const char* cache_path)
         if (rc) return rc;
     }
     if (best_grid >= 0) h->batch_per_cu = best_grid;
-    return SW_OK;
+    return sw_set_merge_width(h, best_merge);
 }
 
 }  // namespace sw

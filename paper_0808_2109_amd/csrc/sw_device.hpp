@@ -1136,8 +1136,7 @@ constexpr uint32_t kK2Empty = 0xFFFFFFFFu;
 
 template <class C>
 struct K2Cfg {
-    static constexpr int NT = (C::FT <= 128) ? 64 : kBlock;    // threads per tile: one wave when the far faces are small (more tiles in flight)
-    static constexpr int KF = (C::FT + NT - 1) / NT;           // face sites per thread (blockDim >= NT)
+    static constexpr int NT = (C::FT <= 128) ? 64 : kBlock;    // default threads per tile: one wave when the far faces are small (more tiles in flight)
     static constexpr int HBITS = (2 * C::FT <= 256) ? 8 : (2 * C::FT <= 512) ? 9 : (2 * C::FT <= 1024) ? 10
                                : (2 * C::FT <= 2048) ? 11 : 12;
     static constexpr int H = 1 << HBITS;   // hash slots: at least twice the face sites
@@ -1186,11 +1185,19 @@ __device__ __forceinline__ void k2_face(int f, int& d, int& fb, int& wbase)
     }
 }
 
-template <class C>
+// The merge schedule: NT threads per tile (the launch's workgroup size, 64 or
+// 256), each with KF far-face sites; the autotuner picks NT.
+template <class C, int NT>
+struct K2Width {
+    static constexpr int KF = (C::FT + NT - 1) / NT;           // face sites per thread
+    static constexpr int H = K2Cfg<C>::H;
+};
+
+template <class C, int NT>
 __device__ void k2_tile(const SwRep& R, int t, K2Smem<C>& sm)
 {
-    using K = K2Cfg<C>;
-    const int tid = threadIdx.x, nt = (int)blockDim.x;
+    using K = K2Width<C, NT>;
+    const int tid = threadIdx.x, nt = NT;
     for (int i = tid; i < K::H; i += nt) sm.keys[i] = kK2Empty;
     for (int i = tid; i < C::XW; i += nt) sm.xb[i] = R.xbits[(size_t)t * C::XW + i];
     if (tid == 0) sm.cnt = 0;

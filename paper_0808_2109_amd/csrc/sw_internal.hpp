@@ -20,7 +20,7 @@ int device_cu_count();
 uint64_t device_wallclock_hz();
 
 int launch_k1(const SwRep& h, SwRep* d, uint32_t s, int64_t* em, hipStream_t stream, int per_cu);
-int launch_k2(const SwRep& h, SwRep* d, hipStream_t stream);
+int launch_k2(const SwRep& h, SwRep* d, hipStream_t stream, int width);
 int launch_k3a(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream);
 int launch_k3(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream, int per_cu);
 int launch_cand(const SwRep& h, SwRep* d, uint32_t s, hipStream_t stream);
@@ -38,7 +38,7 @@ int launch_set_state(SwRep* d, uint32_t sweep, uint32_t measured, uint32_t first
 // (replica, k) for the candidate slots [k * kPercChunk, (k + 1) * kPercChunk)
 int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, int nitems, const EngineItem* cand_items,
                  int ncand, const EngineItem* perc_items, int nperc, int n_sweeps, int any_pcc, int any_series,
-                 int any_3d, int grid, int item_grid, hipStream_t stream);
+                 int any_3d, int grid, int item_grid, int merge_width, hipStream_t stream);
 
 int shape_count(int dim);
 int shape_extents(int dim, int id, int* tx, int* ty, int* tz);

@@ -100,12 +100,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(k1_waves
 }
 
 // K2: one workgroup per tile, grid = ntiles (XCD-aware order)
-template <class C>
-__global__ __launch_bounds__(kBlock) void k2_kernel(const SwRep* Rd)
+template <class C, int NT>
+__global__ __launch_bounds__(NT) void k2_kernel(const SwRep* Rd)
 {
     __shared__ K2Smem<C> sm;
     const SwRep R = *Rd;
-    k2_tile<C>(R, xcd_item(R.ntiles), sm);
+    k2_tile<C, NT>(R, xcd_item(R.ntiles), sm);
 }
 // K3a: one wave per tile, grid = ntiles
 template <class C>
@@ -359,9 +359,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(k1_waves
 }
 
 // K2 over the work list
-template <class C2, class C3, bool LOOP>
-__global__ __launch_bounds__(kBlock) void kb2_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
-                                                     int n_sweeps)
+template <class C2, class C3, bool LOOP, int NT>
+__global__ __launch_bounds__(NT) void kb2_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
+                                                 int n_sweeps)
 {
     __shared__ __align__(16) char smem[cmax2(sizeof(K2Smem<C2>), sizeof(K2Smem<C3>))];
     int i0, i1;
@@ -370,8 +370,8 @@ __global__ __launch_bounds__(kBlock) void kb2_kernel(SwRep* reps, const EngineIt
         const SwRep& R = reps[items[i].rep];
         uint32_t s;
         if (!rep_runs(R, it, n_sweeps, s)) continue;
-        if (R.dim == 2) k2_tile<C2>(R, items[i].tile, *reinterpret_cast<K2Smem<C2>*>(smem));
-        else k2_tile<C3>(R, items[i].tile, *reinterpret_cast<K2Smem<C3>*>(smem));
+        if (R.dim == 2) k2_tile<C2, NT>(R, items[i].tile, *reinterpret_cast<K2Smem<C2>*>(smem));
+        else k2_tile<C3, NT>(R, items[i].tile, *reinterpret_cast<K2Smem<C3>*>(smem));
     }
 }
 
@@ -541,14 +541,17 @@ int launch_k1(const SwRep& h, SwRep* d, uint32_t s, int64_t* em, hipStream_t str
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-int launch_k2(const SwRep& h, SwRep* d, hipStream_t stream)
+// width: threads per tile of the border merge (64 or 256; 0: the tile's default)
+int launch_k2(const SwRep& h, SwRep* d, hipStream_t stream, int width)
 {
     const int grid = h.ntiles;
     switch (h.dim * 16 + h.shape) {
 #define L2(id, D, X, Y, Z)                                                                   \
     case (D * 16 + id): {                                                                    \
         using C = TileCfg<D, X, Y, Z>;                                                       \
-        hipLaunchKernelGGL(k2_kernel<C>, dim3(grid), dim3(K2Cfg<C>::NT), 0, stream, d);      \
+        const int w = width ? width : K2Cfg<C>::NT;                                          \
+        if (w == 64) hipLaunchKernelGGL((k2_kernel<C, 64>), dim3(grid), dim3(64), 0, stream, d); \
+        else hipLaunchKernelGGL((k2_kernel<C, kBlock>), dim3(grid), dim3(kBlock), 0, stream, d); \
         break;                                                                               \
     }
         SW_SHAPES(L2)
@@ -644,12 +647,16 @@ int launch_set_state(SwRep* d, uint32_t sweep, uint32_t measured, uint32_t first
 
 int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, int nitems, const EngineItem* cand_items,
                  int ncand, const EngineItem* perc_items, int nperc, int n_sweeps, int any_pcc, int any_series,
-                 int any_3d, int grid, int item_grid, hipStream_t stream)
+                 int any_3d, int grid, int item_grid, int merge_width, hipStream_t stream)
 {
     const int rgrid = (nreps + kBlock - 1) / kBlock;
     const bool pcc2 = (any_pcc & 1) != 0, pcc3 = (any_pcc & 2) != 0;   // a 2D / 3D PCC replica is active
     const bool loop = item_grid < nitems;                                // workgroups take chunks of the list
     const int ig = item_grid;
+    // border-merge width: the asked one, else one wave for a 2D-only batch whose
+    // tiles have small faces, else 256 threads
+    int k2w = merge_width;
+    if (!k2w) k2w = any_3d ? kBlock : 0;
     switch (variant) {
 #define SW_PHASES(C2, C3, LP)                                                                                        \
     {                                                                                                                \
@@ -662,8 +669,10 @@ int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, i
             hipLaunchKernelGGL((kb1_kernel<C2, C3, false, true, LP>), dim3(ig), b1, 0, stream, reps, items, nitems, it, n_sweeps); \
         else                                                                                                         \
             hipLaunchKernelGGL((kb1_kernel<C2, C3, false, false, LP>), dim3(ig), b1, 0, stream, reps, items, nitems, it, n_sweeps); \
-        hipLaunchKernelGGL((kb2_kernel<C2, C3, LP>), dim3(ig), dim3(any_3d ? kBlock : K2Cfg<C2>::NT), 0, stream, reps,    \
-                           items, nitems, it, n_sweeps);                                                             \
+        if (k2w == 64)                                                                                               \
+            hipLaunchKernelGGL((kb2_kernel<C2, C3, LP, 64>), dim3(ig), dim3(64), 0, stream, reps, items, nitems, it, n_sweeps); \
+        else                                                                                                         \
+            hipLaunchKernelGGL((kb2_kernel<C2, C3, LP, kBlock>), dim3(ig), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
         if (any_pcc && ncand > 0)                                                                                    \
             hipLaunchKernelGGL((kbc_kernel<C2, C3>), dim3(ncand), dim3(kBlock), 0, stream, reps, cand_items, ncand, it, n_sweeps); \
         hipLaunchKernelGGL((kb3a_kernel<C2, C3, LP>), dim3(ig), dim3(64), 0, stream, reps, items, nitems, it, n_sweeps); \
@@ -671,6 +680,7 @@ int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, i
     }
 #define SW_BATCH(i, C2, C3)                                                                                          \
     case i:                                                                                                          \
+        if (!k2w) k2w = K2Cfg<C2>::NT;                                                                               \
         for (int it = 0; it < n_sweeps; ++it) {                                                                      \
             if (loop) SW_PHASES(C2, C3, true) else SW_PHASES(C2, C3, false)                                          \
             if (any_pcc) {                                                                                           \

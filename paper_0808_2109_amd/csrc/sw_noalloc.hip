@@ -145,7 +145,7 @@ extern "C" int sw_sweep_noalloc(const sw_params* params, int8_t* dev_spins, uint
         const uint32_t s = sweep0 + (uint32_t)k;
         // E, M of the configuration after sweep s - 1 are summed by K1 of sweep s
         int64_t* em = (dev_series && k > 0) ? dev_series + 2 * (size_t)(k - 1) : nullptr;
-        if (launch_k1(h, d, s, em, stream, 0) || launch_k2(h, d, stream) || launch_k3a(h, d, s, stream) ||
+        if (launch_k1(h, d, s, em, stream, 0) || launch_k2(h, d, stream, 0) || launch_k3a(h, d, s, stream) ||
             launch_k3(h, d, s, stream, 0))
             return fail(SW_EHIP, "kernel launch failed (sweep %u)", s);
     }

@@ -549,7 +549,7 @@ int plain_sweep(sw_lattice* h, int r, int32_t n)
             m.measured = s;
         }
         TIMED(h, 0, launch_k1(m, d, s, em, h->stream, h->per_cu[0]));
-        TIMED(h, 1, launch_k2(m, d, h->stream));
+        TIMED(h, 1, launch_k2(m, d, h->stream, h->merge_width));
         if (pcc && !(m.flags & FLAG_WIND)) TIMED(h, 3, launch_cand(m, d, s, h->stream));
         TIMED(h, 6, launch_k3a(m, d, s, h->stream));
         TIMED(h, 2, launch_k3(m, d, s, h->stream, h->per_cu[2]));
@@ -677,14 +677,14 @@ int batched_sweep(sw_lattice* h, int32_t n)
     const int per_cu = h->batch_per_cu;
     const int grid = clamp_grid(device_cu_count() * (per_cu > 0 ? per_cu : 8));
     const int item_grid = per_cu > 0 ? clamp_grid(device_cu_count() * per_cu) : h->nitems;
-    if (h->graph_n != n || h->graph_grid != grid || h->graph_item_grid != item_grid ||
+    if (h->graph_n != n || h->graph_grid != grid || h->graph_item_grid != item_grid || h->graph_merge != h->merge_width ||
         h->graph_flags != (int)(any_3d * 8 + pcc_dims * 2 + any_series) || h->graph_variant != variant) {
         drop_graph(h);
         hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
         int lrc = launch_batch(variant, h->d_reps, (int)h->reps.size(), h->items, h->nitems, h->items + h->nitems,
                                h->ncand, h->items + h->nitems + h->ncand, h->nperc, n, pcc_dims, any_series, any_3d,
-                               grid, item_grid, h->stream);
+                               grid, item_grid, h->merge_width, h->stream);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(h->stream, &g);
         if (lrc || e != hipSuccess || !g) {
@@ -700,6 +700,7 @@ int batched_sweep(sw_lattice* h, int32_t n)
         h->graph_n = n;
         h->graph_grid = grid;
         h->graph_item_grid = item_grid;
+        h->graph_merge = h->merge_width;
         h->graph_flags = (int)(any_3d * 8 + pcc_dims * 2 + any_series);
         h->graph_variant = variant;
     }
@@ -821,6 +822,22 @@ int sw_get_batch_grid(sw_lattice* h, int32_t* per_cu)
 {
     if (!h || !per_cu) return fail(SW_EINVAL, "null argument");
     *per_cu = h->batch_per_cu;
+    return SW_OK;
+}
+
+int sw_set_merge_width(sw_lattice* h, int32_t threads)
+{
+    if (!h) return fail(SW_EINVAL, "null handle");
+    if (threads != 0 && threads != 64 && threads != 256)
+        return fail(SW_EINVAL, "border-merge width must be 0, 64 or 256 (got %d)", threads);
+    h->merge_width = threads;
+    return SW_OK;
+}
+
+int sw_get_merge_width(sw_lattice* h, int32_t* threads)
+{
+    if (!h || !threads) return fail(SW_EINVAL, "null argument");
+    *threads = h->merge_width;
     return SW_OK;
 }
 

@@ -67,11 +67,13 @@ struct sw_lattice {
     int nperc = 0;                       // PCC slot chunks (after the candidate list)
     bool items_dirty = true;
     int batch_per_cu = 0;               // workgroups per CU of the batched phase launches (0: one per tile)
+    int merge_width = 0;                // threads per tile of the border merge (0: the tile's default, 64, 256)
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int graph_n = -1;
     int graph_grid = -1;
     int graph_item_grid = -1;
+    int graph_merge = -1;
     int graph_flags = -1;
     int graph_variant = -1;
 };

@@ -76,6 +76,8 @@ def lib():
         "sw_set_mode": (c.c_int, [vp, c.c_int32]),
         "sw_set_batch_grid": (c.c_int, [vp, c.c_int32]),
         "sw_get_batch_grid": (c.c_int, [vp, P(c.c_int32)]),
+        "sw_set_merge_width": (c.c_int, [vp, c.c_int32]),
+        "sw_get_merge_width": (c.c_int, [vp, P(c.c_int32)]),
         "sw_sweep": (c.c_int, [vp, c.c_int32]),
         "sw_sweep_replica": (c.c_int, [vp, c.c_int32, c.c_int32]),
         "sw_measure": (c.c_int, [vp, c.c_int32, P(c.c_int64), P(c.c_int64)]),
@@ -210,6 +212,15 @@ class Lattice:
     def batch_grid(self) -> int:
         v = ctypes.c_int32()
         _check(lib().sw_get_batch_grid(self._h, ctypes.byref(v)))
+        return int(v.value)
+
+    def set_merge_width(self, threads: int):
+        """Threads per tile of the border merge (0: per tile shape, 64 or 256)."""
+        _check(lib().sw_set_merge_width(self._h, threads))
+
+    def merge_width(self) -> int:
+        v = ctypes.c_int32()
+        _check(lib().sw_get_merge_width(self._h, ctypes.byref(v)))
         return int(v.value)
 
     def sweep(self, n: int = 1):

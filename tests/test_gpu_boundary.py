@@ -6,6 +6,7 @@
   abandoned trajectory may survive).
 * sw_bind_device_spins with a torch tensor as the lattice.
 * The batched launch shape (sw_set_batch_grid): results may not depend on it.
+* The border merge's schedule (sw_set_merge_width): neither may it.
 * PCC across tiles in 2D, and at the PCC workload's lattice size (2048^2).
 """
 import numpy as np
@@ -164,6 +165,42 @@ def test_batch_grid_rejects_out_of_range():
             with pytest.raises(swgpu.SwError) as ei:
                 lat.set_batch_grid(bad)
             assert ei.value.code == swgpu.SW_EINVAL
+
+
+@pytest.mark.parametrize("mode", [swgpu.SW_MODE_PLAIN, swgpu.SW_MODE_BATCHED])
+@pytest.mark.parametrize("width", [64, 256])
+def test_merge_width_does_not_change_results(mode, width):
+    """The border merge run with one wave or with 256 threads per tile, in
+    every tile shape, plain and batched: every replica of the mix (2D and 3D,
+    PCC among them) still matches the oracle."""
+    refs = [_oracle(s, 5) for s in MIX]
+    for shape in range(len(swgpu.tile_shapes(2))):
+        with swgpu.Lattice([_params(s) for s in MIX]) as lat:
+            for r in range(len(MIX)):
+                lat.set_tile_shape(r, shape)
+            lat.set_mode(mode)
+            lat.set_merge_width(width)
+            assert lat.merge_width() == width
+            lat.sweep(2)
+            lat.sweep(3)
+            for r, spec in enumerate(MIX):
+                ref = refs[r]
+                tag = f"width {width} mode {mode} shape {shape} replica {r}"
+                assert np.array_equal(lat.spins(r), ref["spins"]), tag
+                assert np.array_equal(lat.labels(r), ref["labels"]), tag
+                assert np.array_equal(lat.series(r), ref["series"]), tag
+                if spec.get("pcc"):
+                    perc, pv = lat.pcc_trace(r)
+                    assert np.array_equal(perc, ref["perc"]) and np.array_equal(pv, ref["p_trace"]), tag
+
+
+def test_merge_width_rejects_other_values():
+    with swgpu.Lattice(_params(dict(dim=2, L=16, T=2.0, seed=1))) as lat:
+        for bad in (-1, 32, 128, 512):
+            with pytest.raises(swgpu.SwError) as ei:
+                lat.set_merge_width(bad)
+            assert ei.value.code == swgpu.SW_EINVAL
+        assert lat.merge_width() == 0
 
 
 @pytest.mark.parametrize("L,shape", [(130, 0), (130, 1), (200, 1)])
