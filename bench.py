@@ -297,6 +297,8 @@ def run_batched(swgpu, workloads, sweeps_batched: int, sweeps_plain: int):
         lat.autotune(sweeps=2)
         out["tile_shape"] = list(swgpu.tile_shapes(2)[lat.tile_shape(0)])
         out["workgroups_per_cu"] = lat.batch_grid()
+        out["engine"] = ("graph", "persistent")[lat.batch_engine()[0]]
+        out["merge_width"] = lat.merge_width()
         lat.sweep(chunk)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -308,6 +310,21 @@ def run_batched(swgpu, workloads, sweeps_batched: int, sweeps_plain: int):
         dt = time.perf_counter() - t0
         out["batched"] = {"site_updates_per_s": sites * sweeps_batched / dt, "sweeps": sweeps_batched,
                           "seconds": dt}
+        # the other batched engine on the same state, for the record (one call
+        # of `chunk` sweeps after an untimed one)
+        engine, _ = lat.batch_engine()
+        other = 1 - engine
+        lat.set_batch_engine(other)
+        lat.sweep(chunk)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.sweep(chunk)
+        torch.cuda.synchronize()
+        dt_other = time.perf_counter() - t0
+        out["engines"] = {out["engine"]: out["batched"]["site_updates_per_s"],
+                          ("graph", "persistent")[other]: sites * chunk / dt_other,
+                          "persistent_grid": lat.batch_engine()[1]}
+        lat.set_batch_engine(engine)
         lat.set_mode(swgpu.SW_MODE_PLAIN)
         lat.sweep(1)
         torch.cuda.synchronize()

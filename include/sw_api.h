@@ -151,6 +151,26 @@ int sw_set_batch_grid(sw_lattice* h, int32_t per_cu);
 /* Current launch shape of batched sweeps (see sw_set_batch_grid). */
 int sw_get_batch_grid(sw_lattice* h, int32_t* per_cu);
 
+/* Batched engines (sw_set_batch_engine). */
+enum {
+    SW_ENGINE_GRAPH = 0,       /* one kernel per phase, n sweeps captured in a replayed hipGraph (default) */
+    SW_ENGINE_PERSISTENT = 1   /* one cooperative launch per call (per 4096 sweeps): resident workgroups walk
+                                  the phases with a software grid barrier between them */
+};
+
+/* Choose how batched sweeps run (Sec. II's sweep for many replicas at once):
+ * both engines run the same per-tile work in the same order of phases and give
+ * identical results.  The persistent engine sizes its grid to the workgroups
+ * that fit on the device at once (or sw_set_batch_grid's per-CU count, if
+ * smaller) and always uses 256-thread border merges.  A barrier that waits
+ * more than 10 s abandons the launch and sets a consistency error, which the
+ * next synchronising call reports as SW_EHIP.  SW_EINVAL for unknown engines. */
+int sw_set_batch_engine(sw_lattice* h, int32_t engine);
+
+/* Current batched engine; grid (may be NULL) receives the workgroups of the
+ * last persistent launch (0 before the first). */
+int sw_get_batch_engine(sw_lattice* h, int32_t* engine, int32_t* grid);
+
 /* Merge schedule of the border merge (the global union across tile faces that
  * reconciles the domains' labels, Sec. II): threads per tile, 64 (one wave per
  * tile: more tiles in flight) or 256 (each thread fewer face sites); 0 picks

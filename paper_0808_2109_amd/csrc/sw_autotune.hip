@@ -8,8 +8,9 @@
 //                  launches on a scratch lattice with the same parameters
 //                  and state;
 //   many replicas: every batched variant (a 2D and a 3D shape), both merge
-//                  widths and four grid sizes are timed on a scratch copy of
-//                  all replicas (parameters and state) in batched mode.
+//                  widths and four grid sizes of the phase-kernel graph, and
+//                  the persistent engine, are timed on a scratch copy of all
+//                  replicas (parameters and state) in batched mode.
 // Choices are cached as JSON keyed by (arch, dim, size class = floor(log2 L))
 // for single lattices and by (arch, "batch", replica count, total sites) for
 // batches.
@@ -34,13 +35,13 @@ static int size_class(int L)
 }
 
 struct Choice {
-    int shape, grid, merge;
+    int shape, grid, merge, engine;
     double ms;
 };
 
 // minimal reader for the cache this file writes:
-// {"key": {"shape": s, "grid": g, "merge": m, ...}, ...}; an entry without
-// "merge" takes the default schedule (0)
+// {"key": {"shape": s, "grid": g, "merge": m, "engine": e, ...}, ...}; an
+// entry without "merge" or "engine" takes the default (0)
 static std::map<std::string, Choice> read_cache(const char* path)
 {
     std::map<std::string, Choice> out;
@@ -63,7 +64,9 @@ static std::map<std::string, Choice> read_cache(const char* path)
         if (sp == std::string::npos || gp == std::string::npos || close == std::string::npos) break;
         const size_t mp = txt.find("\"merge\":", end);
         const int merge = (mp != std::string::npos && mp < close) ? atoi(txt.c_str() + mp + 8) : 0;
-        out[key] = Choice{atoi(txt.c_str() + sp + 8), atoi(txt.c_str() + gp + 7), merge, -1.0};
+        const size_t ep = txt.find("\"engine\":", end);
+        const int engine = (ep != std::string::npos && ep < close) ? atoi(txt.c_str() + ep + 9) : 0;
+        out[key] = Choice{atoi(txt.c_str() + sp + 8), atoi(txt.c_str() + gp + 7), merge, engine, -1.0};
         pos = end + 1;
     }
     return out;
@@ -79,8 +82,8 @@ static void write_cache(const char* path, const std::map<std::string, Choice>& e
     fprintf(f, "{\n");
     size_t i = 0;
     for (auto& kv : all) {
-        fprintf(f, "  \"%s\": {\"shape\": %d, \"grid\": %d, \"merge\": %d, \"ms_per_sweep\": %.6f}%s\n",
-                kv.first.c_str(), kv.second.shape, kv.second.grid, kv.second.merge, kv.second.ms,
+        fprintf(f, "  \"%s\": {\"shape\": %d, \"grid\": %d, \"merge\": %d, \"engine\": %d, \"ms_per_sweep\": %.6f}%s\n",
+                kv.first.c_str(), kv.second.shape, kv.second.grid, kv.second.merge, kv.second.engine, kv.second.ms,
                 (++i < all.size()) ? "," : "");
     }
     fprintf(f, "}\n");
@@ -162,7 +165,7 @@ static int tune_single(sw_lattice* h, int32_t sweeps, const char* cache_path)
         if (rc) return rc;
     }
     std::map<std::string, Choice> out;
-    out[key] = Choice{best, 0, best_merge, best_ms};
+    out[key] = Choice{best, 0, best_merge, 0, best_ms};
     write_cache(cache_path, out);
     int rc = sw_set_tile_shape(h, 0, best);
     return rc ? rc : sw_set_merge_width(h, best_merge);
@@ -174,7 +177,7 @@ static int tune_batch(sw_lattice* h, int32_t sweeps, const char* cache_path)
     for (auto& r : h->reps) total += r.h.N;
     char key[96];
     snprintf(key, sizeof(key), "gfx950:batch:r%zu:n%llu", h->reps.size(), (unsigned long long)total);
-    int best_v = 0, best_grid = 0, best_merge = 0;
+    int best_v = 0, best_grid = 0, best_merge = 0, best_engine = SW_ENGINE_GRAPH;
     double best_ms = 1e30;
     auto cached = read_cache(cache_path);
     auto it = cached.find(key);
@@ -182,6 +185,7 @@ static int tune_batch(sw_lattice* h, int32_t sweeps, const char* cache_path)
         best_v = it->second.shape;
         best_grid = it->second.grid;
         best_merge = it->second.merge;
+        best_engine = it->second.engine == SW_ENGINE_PERSISTENT ? SW_ENGINE_PERSISTENT : SW_ENGINE_GRAPH;
     } else {
         std::vector<sw_params> ps;
         for (auto& r : h->reps) {
@@ -207,14 +211,30 @@ static int tune_batch(sw_lattice* h, int32_t sweeps, const char* cache_path)
                         best_v = v;
                         best_grid = per_cu;
                         best_merge = merge;
+                        best_engine = SW_ENGINE_GRAPH;
                     }
+                }
+            }
+            if (!rc) {
+                // the persistent engine, with as many workgroups as fit
+                s->batch_engine = SW_ENGINE_PERSISTENT;
+                s->batch_per_cu = 0;
+                s->merge_width = 0;
+                double ms = 0;
+                rc = time_sweeps(s, sweeps, &ms);
+                if (!rc && ms < best_ms) {
+                    best_ms = ms;
+                    best_v = v;
+                    best_grid = 0;
+                    best_merge = 0;
+                    best_engine = SW_ENGINE_PERSISTENT;
                 }
             }
             if (s) sw_free(s);
             if (rc) return rc;
         }
         std::map<std::string, Choice> out;
-        out[key] = Choice{best_v, best_grid, best_merge, best_ms};
+        out[key] = Choice{best_v, best_grid, best_merge, best_engine, best_ms};
         write_cache(cache_path, out);
     }
     for (size_t r = 0; r < h->reps.size(); ++r) {
@@ -222,6 +242,7 @@ static int tune_batch(sw_lattice* h, int32_t sweeps, const char* cache_path)
         if (rc) return rc;
     }
     if (best_grid >= 0) h->batch_per_cu = best_grid;
+    h->batch_engine = best_engine;
     return sw_set_merge_width(h, best_merge);
 }
 

@@ -91,7 +91,7 @@ struct SwRep {
 
 // consistency checks on data-dependent indices: a violation sets a bit that
 // the host turns into an error instead of letting the access go out of range
-enum : int { ERR_TILE_LABEL = 1, ERR_PARENT = 2, ERR_SLOT = 3, ERR_WIND_RANGE = 4 };
+enum : int { ERR_TILE_LABEL = 1, ERR_PARENT = 2, ERR_SLOT = 3, ERR_WIND_RANGE = 4, ERR_BARRIER = 5 };
 
 __device__ __forceinline__ void flag_error(const SwRep& R, int code)
 {

@@ -332,9 +332,101 @@ __device__ __forceinline__ void item_range(int nitems, int& i0, int& i1)
     }
 }
 
+// One work item of each phase, shared by the phase kernels (one launch per
+// phase) and the persistent kernel (all phases in one launch).
 // (P2, P3: the PCC instantiation of the 2D / 3D tile labelling, chosen when
 // a 2D / 3D PCC replica is active, so that the shared memory is sized for
 // what the batch needs)
+template <class C2, class C3, bool P2, bool P3>
+__device__ __forceinline__ void k1_item(const SwRep* reps, const EngineItem& item, int it, int n_sweeps, char* smem)
+{
+    const SwRep& R = reps[item.rep];
+    uint32_t s;
+    if (!rep_runs(R, it, n_sweeps, s)) return;
+    int64_t* dst = nullptr;
+    if ((R.flags & FLAG_SERIES) && s >= 1 && (it > 0 || R.measured < R.sweep))
+        dst = R.series + 2 * (size_t)(s - 1 - R.first);
+    int64_t e = 0, m = 0;
+    if (R.dim == 2)
+        k1_tile<C2, P2>(R, item.tile, s, R.thr, *reinterpret_cast<K1Smem<C2, P2>*>(smem), dst != nullptr, e, m);
+    else
+        k1_tile<C3, P3>(R, item.tile, s, R.thr, *reinterpret_cast<K1Smem<C3, P3>*>(smem), dst != nullptr, e, m);
+    if (dst) wave_flush_em(e, m, dst);
+}
+
+template <class C2, class C3, int NT>
+__device__ __forceinline__ void k2_item(const SwRep* reps, const EngineItem& item, int it, int n_sweeps, char* smem)
+{
+    const SwRep& R = reps[item.rep];
+    uint32_t s;
+    if (!rep_runs(R, it, n_sweeps, s)) return;
+    if (R.dim == 2) k2_tile<C2, NT>(R, item.tile, *reinterpret_cast<K2Smem<C2>*>(smem));
+    else k2_tile<C3, NT>(R, item.tile, *reinterpret_cast<K2Smem<C3>*>(smem));
+}
+
+// PCC candidates of one tile of the candidate list
+template <class C2, class C3>
+__device__ __forceinline__ void kc_item(const SwRep* reps, const EngineItem& item, int it, int n_sweeps)
+{
+    const SwRep R = reps[item.rep];
+    uint32_t s;
+    if ((R.flags & (FLAG_PCC | FLAG_WIND)) != FLAG_PCC || !rep_runs(R, it, n_sweeps, s)) return;
+    if (R.dim == 2) k_cand_tile<C2>(R, item.tile, s);
+    else k_cand_tile<C3>(R, item.tile, s);
+}
+
+// border-root resolution of one tile by one wave (smem: that wave's tables)
+template <class C2, class C3>
+__device__ __forceinline__ void k3a_item(const SwRep* reps, const EngineItem& item, int it, int n_sweeps, char* smem)
+{
+    const SwRep& R = reps[item.rep];
+    uint32_t s;
+    if (!rep_runs(R, it, n_sweeps, s)) return;
+    wave_lds_sync();   // the previous item's reads of the tables are done
+    CovArgs cov;
+    if (R.dim == 2) k3a_tile<C2>(R, item.tile, s, *reinterpret_cast<K3aSmem<C2>*>(smem), cov);
+    else k3a_tile<C3>(R, item.tile, s, *reinterpret_cast<K3aSmem<C3>*>(smem), cov);
+    if (cov.nl >= 0) k3a_coverage(cov);
+}
+
+template <class C2, class C3>
+__device__ __forceinline__ void k3_item(const SwRep* reps, const EngineItem& item, int it, int n_sweeps, char* smem)
+{
+    const SwRep& R = reps[item.rep];
+    uint32_t s;
+    if (!rep_runs(R, it, n_sweeps, s)) return;
+    if (R.dim == 2) k3_tile<C2>(R, item.tile, s, *reinterpret_cast<K3Smem<C2>*>(smem));
+    else k3_tile<C3>(R, item.tile, s, *reinterpret_cast<K3Smem<C3>*>(smem));
+}
+
+// PCC coverage test of one item of the slot list: item (replica, k) stands
+// for the candidate slots [k * kPercChunk, (k + 1) * kPercChunk) of every axis
+// of that replica (the whole workgroup; pflag_local in shared memory)
+__device__ __forceinline__ void perc_item(const SwRep* reps, const EngineItem& item, int it, int n_sweeps,
+                                          int* pflag_local)
+{
+    const SwRep R = reps[item.rep];
+    uint32_t s;
+    if ((R.flags & (FLAG_PCC | FLAG_WIND)) != FLAG_PCC || !rep_runs(R, it, n_sweeps, s)) return;
+    const uint32_t nslots = (R.dim == 3) ? (uint32_t)R.L * (uint32_t)R.L : (uint32_t)R.L;
+    const uint32_t c0 = min(nslots, (uint32_t)item.tile * (uint32_t)kPercChunk);
+    const uint32_t c1 = min(nslots, c0 + (uint32_t)kPercChunk);
+    if (threadIdx.x == 0) *pflag_local = 0;
+    __syncthreads();
+    perc_chunk(R, c0, c1, pflag_local);
+    __syncthreads();
+    if (threadIdx.x == 0 && *pflag_local) atomicOr(R.pflag, 1);
+}
+
+// PCC feedback of replica r
+__device__ __forceinline__ void update_rep(SwRep* reps, int r, int it, int n_sweeps)
+{
+    SwRep* Rp = &reps[r];
+    uint32_t s;
+    if (!(Rp->flags & FLAG_PCC) || !rep_runs(*Rp, it, n_sweeps, s)) return;
+    pcc_update(Rp, s);
+}
+
 template <class C2, class C3, bool P2, bool P3, bool LOOP>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(k1_waves<C2>()))) void kb1_kernel(
     SwRep* reps, const EngineItem* items, int nitems, int it, int n_sweeps)
@@ -342,20 +434,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(k1_waves
     __shared__ __align__(16) char smem[cmax2(sizeof(K1Smem<C2, P2>), sizeof(K1Smem<C3, P3>))];
     int i0, i1;
     item_range<LOOP>(nitems, i0, i1);
-    for (int i = i0; i < i1; ++i) {
-        const SwRep& R = reps[items[i].rep];
-        uint32_t s;
-        if (!rep_runs(R, it, n_sweeps, s)) continue;
-        int64_t* dst = nullptr;
-        if ((R.flags & FLAG_SERIES) && s >= 1 && (it > 0 || R.measured < R.sweep))
-            dst = R.series + 2 * (size_t)(s - 1 - R.first);
-        int64_t e = 0, m = 0;
-        if (R.dim == 2)
-            k1_tile<C2, P2>(R, items[i].tile, s, R.thr, *reinterpret_cast<K1Smem<C2, P2>*>(smem), dst != nullptr, e, m);
-        else
-            k1_tile<C3, P3>(R, items[i].tile, s, R.thr, *reinterpret_cast<K1Smem<C3, P3>*>(smem), dst != nullptr, e, m);
-        if (dst) wave_flush_em(e, m, dst);
-    }
+    for (int i = i0; i < i1; ++i) k1_item<C2, C3, P2, P3>(reps, items[i], it, n_sweeps, smem);
 }
 
 // K2 over the work list
@@ -366,13 +445,7 @@ __global__ __launch_bounds__(NT) void kb2_kernel(SwRep* reps, const EngineItem* 
     __shared__ __align__(16) char smem[cmax2(sizeof(K2Smem<C2>), sizeof(K2Smem<C3>))];
     int i0, i1;
     item_range<LOOP>(nitems, i0, i1);
-    for (int i = i0; i < i1; ++i) {
-        const SwRep& R = reps[items[i].rep];
-        uint32_t s;
-        if (!rep_runs(R, it, n_sweeps, s)) continue;
-        if (R.dim == 2) k2_tile<C2, NT>(R, items[i].tile, *reinterpret_cast<K2Smem<C2>*>(smem));
-        else k2_tile<C3, NT>(R, items[i].tile, *reinterpret_cast<K2Smem<C3>*>(smem));
-    }
+    for (int i = i0; i < i1; ++i) k2_item<C2, C3, NT>(reps, items[i], it, n_sweeps, smem);
 }
 
 // PCC candidates: one workgroup per item of the candidate list, which holds
@@ -382,12 +455,7 @@ __global__ __launch_bounds__(kBlock) void kbc_kernel(SwRep* reps, const EngineIt
                                                      int n_sweeps)
 {
     const int i = (int)blockIdx.x;
-    if (i >= nitems) return;
-    const SwRep R = reps[items[i].rep];
-    uint32_t s;
-    if ((R.flags & (FLAG_PCC | FLAG_WIND)) != FLAG_PCC || !rep_runs(R, it, n_sweeps, s)) return;
-    if (R.dim == 2) k_cand_tile<C2>(R, items[i].tile, s);
-    else k_cand_tile<C3>(R, items[i].tile, s);
+    if (i < nitems) kc_item<C2, C3>(reps, items[i], it, n_sweeps);
 }
 
 template <class C2, class C3, bool LOOP>
@@ -397,16 +465,7 @@ __global__ __launch_bounds__(64) void kb3a_kernel(SwRep* reps, const EngineItem*
     __shared__ __align__(16) char smem[cmax2(sizeof(K3aSmem<C2>), sizeof(K3aSmem<C3>))];
     int i0, i1;
     item_range<LOOP>(nitems, i0, i1);
-    for (int i = i0; i < i1; ++i) {
-        const SwRep& R = reps[items[i].rep];
-        uint32_t s;
-        if (!rep_runs(R, it, n_sweeps, s)) continue;
-        wave_lds_sync();   // the previous item's reads of the tables are done
-        CovArgs cov;
-        if (R.dim == 2) k3a_tile<C2>(R, items[i].tile, s, *reinterpret_cast<K3aSmem<C2>*>(smem), cov);
-        else k3a_tile<C3>(R, items[i].tile, s, *reinterpret_cast<K3aSmem<C3>*>(smem), cov);
-        if (cov.nl >= 0) k3a_coverage(cov);
-    }
+    for (int i = i0; i < i1; ++i) k3a_item<C2, C3>(reps, items[i], it, n_sweeps, smem);
 }
 
 template <class C2, class C3, bool LOOP>
@@ -416,46 +475,23 @@ __global__ __launch_bounds__(kK3Block) void kb3_kernel(SwRep* reps, const Engine
     __shared__ __align__(16) char smem[cmax2(sizeof(K3Smem<C2>), sizeof(K3Smem<C3>))];
     int i0, i1;
     item_range<LOOP>(nitems, i0, i1);
-    for (int i = i0; i < i1; ++i) {
-        const SwRep& R = reps[items[i].rep];
-        uint32_t s;
-        if (!rep_runs(R, it, n_sweeps, s)) continue;
-        if (R.dim == 2) k3_tile<C2>(R, items[i].tile, s, *reinterpret_cast<K3Smem<C2>*>(smem));
-        else k3_tile<C3>(R, items[i].tile, s, *reinterpret_cast<K3Smem<C3>*>(smem));
-    }
+    for (int i = i0; i < i1; ++i) k3_item<C2, C3>(reps, items[i], it, n_sweeps, smem);
 }
 
-// PCC coverage test: one workgroup per item of the slot list, whose item
-// (replica, k) stands for the candidate slots [k * kPercChunk, (k + 1) *
-// kPercChunk) of every axis of that replica
+// PCC coverage test: one workgroup per item of the slot list
 __global__ __launch_bounds__(kBlock) void kbp_kernel(SwRep* reps, const EngineItem* items, int nitems, int it,
                                                      int n_sweeps)
 {
     __shared__ int pflag_local;
     const int i = (int)blockIdx.x;
-    if (i >= nitems) return;
-    const SwRep R = reps[items[i].rep];
-    uint32_t s;
-    if ((R.flags & (FLAG_PCC | FLAG_WIND)) != FLAG_PCC || !rep_runs(R, it, n_sweeps, s)) return;
-    const uint32_t nslots = (R.dim == 3) ? (uint32_t)R.L * (uint32_t)R.L : (uint32_t)R.L;
-    const uint32_t c0 = min(nslots, (uint32_t)items[i].tile * (uint32_t)kPercChunk);
-    const uint32_t c1 = min(nslots, c0 + (uint32_t)kPercChunk);
-    if (threadIdx.x == 0) pflag_local = 0;
-    __syncthreads();
-    perc_chunk(R, c0, c1, &pflag_local);
-    __syncthreads();
-    if (threadIdx.x == 0 && pflag_local) atomicOr(R.pflag, 1);
+    if (i < nitems) perc_item(reps, items[i], it, n_sweeps, &pflag_local);
 }
 
 // PCC feedback: one thread per replica
 __global__ __launch_bounds__(kBlock) void kbu_kernel(SwRep* reps, int nreps, int it, int n_sweeps)
 {
     const int r = blockIdx.x * kBlock + threadIdx.x;
-    if (r >= nreps) return;
-    SwRep* Rp = &reps[r];
-    uint32_t s;
-    if (!(Rp->flags & FLAG_PCC) || !rep_runs(*Rp, it, n_sweeps, s)) return;
-    pcc_update(Rp, s);
+    if (r < nreps) update_rep(reps, r, it, n_sweeps);
 }
 
 // E, M after the last sweep of every recording replica
@@ -502,6 +538,165 @@ __global__ __launch_bounds__(kBlock) void kbfin_kernel(SwRep* reps, int nreps, i
     if (Rp->flags & FLAG_SERIES) Rp->measured = (uint32_t)max((uint64_t)Rp->measured, target);
     Rp->sweep = (uint32_t)target;
 }
+// ---------------------------------------------------------------------------
+// Persistent batched engine: one cooperative launch runs all n sweeps.  Every
+// workgroup of the grid is resident at once; each walks its XCD-aware chunk
+// of the work list phase by phase, and a software grid barrier stands where
+// the phase kernels have a kernel boundary.  The barrier waits a bounded time:
+// past it the workgroup sets ERR_BARRIER in the error word and every
+// workgroup leaves at its next barrier, so the launch always ends.
+// ---------------------------------------------------------------------------
+struct PersistArgs {
+    SwRep* reps;
+    const EngineItem* items;
+    const EngineItem* cand;
+    const EngineItem* perc;
+    uint32_t* bar;          // arrivals, zero at launch
+    uint32_t* queue;        // one work counter per XCD, zero at launch
+    int32_t* err;           // the handle's error word
+    uint64_t limit;         // wall-clock ticks a workgroup waits at a barrier
+    int nreps, nitems, ncand, nperc, n_sweeps, any_pcc;
+};
+
+// arrive, wait for the whole grid, then see every workgroup's writes; true
+// when the launch is being abandoned
+__device__ __forceinline__ bool grid_sync(const PersistArgs& A, uint32_t& target, int* abort_flag)
+{
+    __threadfence();   // this thread's writes are visible device-wide before it arrives
+    __syncthreads();
+    target += gridDim.x;
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(A.bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t t0 = wall_clock64();
+        int ab = 0;
+        while (__hip_atomic_load(A.bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(A.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (1 << ERR_BARRIER)) {
+                ab = 1;
+                break;
+            }
+            if (wall_clock64() - t0 > A.limit) {
+                atomicOr(A.err, 1 << ERR_BARRIER);
+                ab = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        *abort_flag = ab;
+    }
+    __syncthreads();
+    __threadfence();   // acquire: this workgroup's later loads see the others' writes
+    return *abort_flag != 0;
+}
+
+// Dynamic work distribution: the work list is cut into one contiguous range
+// per XCD (workgroup b runs on XCD b % 8, so neighbouring tiles stay in one
+// L2), and the workgroups (or waves) of an XCD take the items of its range
+// one at a time from a shared counter.  The counter only grows: every taker
+// ends each phase with exactly one draw past the range, so after a phase the
+// counter has grown by the range's length plus the number of takers, which
+// every taker adds to its own copy of the base.
+struct WorkQueue {
+    uint32_t* ctr;
+    uint32_t base;
+    int lo, n;            // this XCD's range of the work list
+    int block_takers;     // workgroups drawing from this counter
+};
+
+__device__ __forceinline__ WorkQueue make_queue(const PersistArgs& A)
+{
+    const int G = (int)gridDim.x;
+    const int nq = (G % 8 == 0) ? 8 : 1;
+    const int x = (int)blockIdx.x % nq;
+    WorkQueue Q;
+    Q.ctr = A.queue + x;
+    Q.base = 0;
+    Q.lo = (int)(((int64_t)x * A.nitems) / nq);
+    Q.n = (int)(((int64_t)(x + 1) * A.nitems) / nq) - Q.lo;
+    Q.block_takers = G / nq;
+    return Q;
+}
+
+// next item for the whole workgroup, or -1 when the range is done
+__device__ __forceinline__ int take_block(WorkQueue& Q, int* slot)
+{
+    __syncthreads();   // every thread has read the previous draw
+    if (threadIdx.x == 0) *slot = (int)(atomicAdd(Q.ctr, 1u) - Q.base);
+    __syncthreads();
+    const int k = *slot;
+    if (k >= Q.n) {
+        Q.base += (uint32_t)(Q.n + Q.block_takers);
+        return -1;
+    }
+    return Q.lo + k;
+}
+
+// next item for this wave alone, or -1 when the range is done
+__device__ __forceinline__ int take_wave(WorkQueue& Q)
+{
+    uint32_t v = 0;
+    if ((threadIdx.x & 63) == 0) v = atomicAdd(Q.ctr, 1u);
+    const int k = (int)(__shfl(v, 0, 64) - Q.base);
+    if (k >= Q.n) {
+        Q.base += (uint32_t)(Q.n + Q.block_takers * (kBlock / 64));
+        return -1;
+    }
+    return Q.lo + k;
+}
+
+template <class C2, class C3>
+constexpr size_t k3a_slot() { return (cmax2(sizeof(K3aSmem<C2>), sizeof(K3aSmem<C3>)) + 15) & ~(size_t)15; }
+
+template <class C2, class C3, bool P2, bool P3>
+constexpr size_t persist_smem()
+{
+    return cmax2(cmax2(cmax2(sizeof(K1Smem<C2, P2>), sizeof(K1Smem<C3, P3>)),
+                       cmax2(sizeof(K2Smem<C2>), sizeof(K2Smem<C3>))),
+                 cmax2((kBlock / 64) * k3a_slot<C2, C3>(), cmax2(sizeof(K3Smem<C2>), sizeof(K3Smem<C3>))));
+}
+
+template <class C2, class C3, bool P2, bool P3>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void kpersist_kernel(PersistArgs A)
+{
+    static_assert(kK3Block == kBlock, "the flip phase runs on the persistent workgroup");
+    __shared__ __align__(16) char smem[persist_smem<C2, C3, P2, P3>()];
+    __shared__ int abort_flag, pflag_local, slot;
+    uint32_t target = 0;
+    WorkQueue Q = make_queue(A);
+    const int wave = (int)threadIdx.x >> 6;
+    for (int it = 0; it < A.n_sweeps; ++it) {
+        for (int i; (i = take_block(Q, &slot)) >= 0;) k1_item<C2, C3, P2, P3>(A.reps, A.items[i], it, A.n_sweeps, smem);
+        if (grid_sync(A, target, &abort_flag)) return;
+        for (int i; (i = take_block(Q, &slot)) >= 0;) k2_item<C2, C3, kBlock>(A.reps, A.items[i], it, A.n_sweeps, smem);
+        if (grid_sync(A, target, &abort_flag)) return;
+        if (A.any_pcc && A.ncand > 0) {
+            for (int i = (int)blockIdx.x; i < A.ncand; i += (int)gridDim.x)
+                kc_item<C2, C3>(A.reps, A.cand[i], it, A.n_sweeps);
+            if (grid_sync(A, target, &abort_flag)) return;
+        }
+        // one wave per tile, each wave with its own tables
+        for (int i; (i = take_wave(Q)) >= 0;)
+            k3a_item<C2, C3>(A.reps, A.items[i], it, A.n_sweeps, smem + wave * k3a_slot<C2, C3>());
+        if (grid_sync(A, target, &abort_flag)) return;
+        for (int i; (i = take_block(Q, &slot)) >= 0;) k3_item<C2, C3>(A.reps, A.items[i], it, A.n_sweeps, smem);
+        if (grid_sync(A, target, &abort_flag)) return;
+        if (A.any_pcc) {
+            for (int i = (int)blockIdx.x; i < A.nperc; i += (int)gridDim.x)
+                perc_item(A.reps, A.perc[i], it, A.n_sweeps, &pflag_local);
+            if (grid_sync(A, target, &abort_flag)) return;
+            for (int r = (int)(blockIdx.x * kBlock + threadIdx.x); r < A.nreps; r += (int)(gridDim.x * kBlock))
+                update_rep(A.reps, r, it, A.n_sweeps);
+            if (grid_sync(A, target, &abort_flag)) return;
+        }
+    }
+}
+
+// zero the barrier word and the per-XCD work counters
+__global__ void kbar_reset_kernel(uint32_t* bar, uint32_t* queue)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *bar = 0u;
+    if (blockIdx.x == 0 && threadIdx.x < 8) queue[threadIdx.x] = 0u;
+}
+
 // ---------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------
@@ -695,6 +890,79 @@ int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, i
     }
     if (any_series) hipLaunchKernelGGL(kbm_kernel, dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, n_sweeps);
     hipLaunchKernelGGL(kbfin_kernel, dim3(rgrid), dim3(kBlock), 0, stream, reps, nreps, n_sweeps);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+template <class C2, class C3>
+static const void* persist_fn(bool pcc2, bool pcc3)
+{
+    if (pcc2 && pcc3) return reinterpret_cast<const void*>(&kpersist_kernel<C2, C3, true, true>);
+    if (pcc2) return reinterpret_cast<const void*>(&kpersist_kernel<C2, C3, true, false>);
+    if (pcc3) return reinterpret_cast<const void*>(&kpersist_kernel<C2, C3, false, true>);
+    return reinterpret_cast<const void*>(&kpersist_kernel<C2, C3, false, false>);
+}
+
+// Sweeps per persistent launch: at most 4096, and few enough that the
+// barrier's arrival count (at most 7 barriers a sweep, times the grid) and
+// the work counters (4 phases a sweep, each the XCD's range plus one draw per
+// taker) stay below 2^31.
+static int persist_chunk(int nitems, int grid)
+{
+    const int64_t per_sweep = std::max<int64_t>(7ll * grid, 4ll * (nitems + 4ll * grid + 8));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(4096, (int64_t(1) << 31) / per_sweep));
+}
+
+int launch_persistent(int variant, SwRep* reps, int nreps, const EngineItem* items, int nitems,
+                      const EngineItem* cand_items, int ncand, const EngineItem* perc_items, int nperc, int n_sweeps,
+                      int any_pcc, int any_series, int per_cu, uint32_t* bar, int32_t* err, hipStream_t stream,
+                      int* grid_used)
+{
+    const bool pcc2 = (any_pcc & 1) != 0, pcc3 = (any_pcc & 2) != 0;
+    const void* fn = nullptr;
+    switch (variant) {
+#define SW_PERSIST(i, C2, C3) \
+    case i: fn = persist_fn<C2, C3>(pcc2, pcc3); break;
+        SW_ENGINE_PAIRS(SW_PERSIST)
+#undef SW_PERSIST
+        default: return -1;
+    }
+    int dev = 0, resident = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -3;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, fn, kBlock, 0) != hipSuccess || resident < 1) return -3;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) return -3;
+    // every workgroup must be resident: at most `resident` per CU
+    const int cus = device_cu_count();
+    int grid = cus * ((per_cu > 0 && per_cu < resident) ? per_cu : resident);
+    if (grid > nitems) grid = nitems;
+    if (grid >= 8) grid -= grid % 8;
+    if (grid < 1) grid = 1;
+    PersistArgs a;
+    a.reps = reps;
+    a.items = items;
+    a.cand = cand_items;
+    a.perc = perc_items;
+    a.bar = bar;
+    a.queue = bar + 16;
+    a.err = err;
+    a.limit = (uint64_t)khz * 1000ull * 10ull;   // 10 s at a barrier
+    a.nreps = nreps;
+    a.nitems = nitems;
+    a.ncand = ncand;
+    a.nperc = nperc;
+    a.any_pcc = any_pcc;
+    const int rgrid = (nreps + kBlock - 1) / kBlock;
+    const int chunk = persist_chunk(nitems, grid);
+    for (int done = 0; done < n_sweeps;) {
+        const int n = min(chunk, n_sweeps - done);
+        a.n_sweeps = n;
+        hipLaunchKernelGGL(kbar_reset_kernel, dim3(1), dim3(64), 0, stream, bar, a.queue);
+        void* args[] = {&a};
+        if (hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kBlock), args, 0, stream) != hipSuccess) return -3;
+        if (any_series) hipLaunchKernelGGL(kbm_kernel, dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, n);
+        hipLaunchKernelGGL(kbfin_kernel, dim3(rgrid), dim3(kBlock), 0, stream, reps, nreps, n);
+        done += n;
+    }
+    if (grid_used) *grid_used = grid;
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

@@ -675,6 +675,19 @@ int batched_sweep(sw_lattice* h, int32_t n)
         return g < 1 ? 1 : g;
     };
     const int per_cu = h->batch_per_cu;
+    if (h->batch_engine == SW_ENGINE_PERSISTENT) {
+        hipEvent_t ev;
+        timing_begin(h, 5, &ev);
+        int lrc = launch_persistent(variant, h->d_reps, (int)h->reps.size(), h->items, h->nitems, h->items + h->nitems,
+                                    h->ncand, h->items + h->nitems + h->ncand, h->nperc, n, pcc_dims, any_series,
+                                    per_cu, h->bar, h->err, h->stream, &h->persist_grid);
+        timing_end(h, 5, ev);
+        if (lrc) return fail(SW_EHIP, "persistent batched launch failed (%d)", lrc);
+        h->mirror_stale = true;
+        for (auto& rep : h->reps)
+            if (rep.h.active) rep.labels_valid = true;
+        return SW_OK;
+    }
     const int grid = clamp_grid(device_cu_count() * (per_cu > 0 ? per_cu : 8));
     const int item_grid = per_cu > 0 ? clamp_grid(device_cu_count() * per_cu) : h->nitems;
     if (h->graph_n != n || h->graph_grid != grid || h->graph_item_grid != item_grid || h->graph_merge != h->merge_width ||
@@ -774,9 +787,11 @@ int sw_init(const sw_params* params, int32_t n_replicas, int32_t device, void* h
     int rc = SW_OK;
     for (int32_t r = 0; r < n_replicas && !rc; ++r) rc = replica_alloc(h->reps[r], &params[r], default_shape(params[r].dim), h->stream);
     if (!rc) rc = dmalloc((void**)&h->d_reps, sizeof(SwRep) * (size_t)n_replicas, "replica descriptors");
-    if (!rc) rc = dmalloc((void**)&h->err, sizeof(int32_t), "consistency-check word");
-    if (!rc && hipMemsetAsync(h->err, 0, sizeof(int32_t), h->stream) != hipSuccess)
+    // the error word, and 128 bytes further the persistent engine's barrier word
+    if (!rc) rc = dmalloc((void**)&h->err, 256, "consistency-check and barrier words");
+    if (!rc && hipMemsetAsync(h->err, 0, 256, h->stream) != hipSuccess)
         rc = fail(SW_EHIP, "clearing the consistency-check word");
+    if (!rc) h->bar = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(h->err) + 128);
     if (!rc) {
         std::vector<SwRep> tmp(n_replicas);
         for (int32_t r = 0; r < n_replicas; ++r) {
@@ -822,6 +837,23 @@ int sw_get_batch_grid(sw_lattice* h, int32_t* per_cu)
 {
     if (!h || !per_cu) return fail(SW_EINVAL, "null argument");
     *per_cu = h->batch_per_cu;
+    return SW_OK;
+}
+
+int sw_set_batch_engine(sw_lattice* h, int32_t engine)
+{
+    if (!h) return fail(SW_EINVAL, "null handle");
+    if (engine != SW_ENGINE_GRAPH && engine != SW_ENGINE_PERSISTENT)
+        return fail(SW_EINVAL, "unknown batched engine %d", engine);
+    h->batch_engine = engine;
+    return SW_OK;
+}
+
+int sw_get_batch_engine(sw_lattice* h, int32_t* engine, int32_t* grid)
+{
+    if (!h || !engine) return fail(SW_EINVAL, "null argument");
+    *engine = h->batch_engine;
+    if (grid) *grid = h->persist_grid;
     return SW_OK;
 }
 

@@ -52,6 +52,7 @@ struct sw_lattice {
     std::vector<sw::ReplicaH> reps;
     sw::SwRep* d_reps = nullptr;        // device descriptor array
     int32_t* err = nullptr;             // device consistency-check word shared by the replicas
+    uint32_t* bar = nullptr;            // grid-barrier word of the persistent batched engine (same allocation)
     bool mirror_stale = false;          // device-side counters changed since the last read
     // timing
     bool timing = false;
@@ -68,6 +69,8 @@ struct sw_lattice {
     bool items_dirty = true;
     int batch_per_cu = 0;               // workgroups per CU of the batched phase launches (0: one per tile)
     int merge_width = 0;                // threads per tile of the border merge (0: the tile's default, 64, 256)
+    int batch_engine = SW_ENGINE_GRAPH; // phase kernels replayed from a graph, or one persistent launch
+    int persist_grid = 0;               // workgroups of the last persistent launch
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int graph_n = -1;

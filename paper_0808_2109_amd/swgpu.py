@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libswgpu.so")
 SW_OK, SW_EINVAL, SW_ENOMEM, SW_EHIP, SW_EBUSY, SW_ENOTFOUND, SW_ECANCELLED, SW_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
 SW_RECORD_SERIES, SW_KEEP_LABELS, SW_PCC, SW_BITPACK, SW_OPEN, SW_PCC_WIND = 1, 2, 4, 8, 16, 32
 SW_MODE_PLAIN, SW_MODE_BATCHED = 0, 1
+SW_ENGINE_GRAPH, SW_ENGINE_PERSISTENT = 0, 1
 JOB_STATES = {0: "queued", 1: "running", 2: "done", 3: "rejected", 4: "cancelled"}
 PHASES = ("k1_bond_label", "k2_merge", "k3_flip", "pcc", "measure", "batched", "k3_resolve")
 
@@ -77,6 +78,8 @@ def lib():
         "sw_set_batch_grid": (c.c_int, [vp, c.c_int32]),
         "sw_get_batch_grid": (c.c_int, [vp, P(c.c_int32)]),
         "sw_set_merge_width": (c.c_int, [vp, c.c_int32]),
+        "sw_set_batch_engine": (c.c_int, [vp, c.c_int32]),
+        "sw_get_batch_engine": (c.c_int, [vp, P(c.c_int32), P(c.c_int32)]),
         "sw_get_merge_width": (c.c_int, [vp, P(c.c_int32)]),
         "sw_sweep": (c.c_int, [vp, c.c_int32]),
         "sw_sweep_replica": (c.c_int, [vp, c.c_int32, c.c_int32]),
@@ -213,6 +216,16 @@ class Lattice:
         v = ctypes.c_int32()
         _check(lib().sw_get_batch_grid(self._h, ctypes.byref(v)))
         return int(v.value)
+
+    def set_batch_engine(self, engine: int):
+        """SW_ENGINE_GRAPH (phase kernels in a replayed graph) or SW_ENGINE_PERSISTENT."""
+        _check(lib().sw_set_batch_engine(self._h, engine))
+
+    def batch_engine(self):
+        """(engine, workgroups of the last persistent launch)."""
+        e, g = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().sw_get_batch_engine(self._h, ctypes.byref(e), ctypes.byref(g)))
+        return int(e.value), int(g.value)
 
     def set_merge_width(self, threads: int):
         """Threads per tile of the border merge (0: per tile shape, 64 or 256)."""

@@ -103,7 +103,7 @@ def test_autotune_keeps_trajectories(tmp_path):
     import json
 
     entries = json.load(open(cache))
-    assert entries and all(e["merge"] in (64, 256) for e in entries.values())
+    assert entries and all(e["merge"] in (0, 64, 256) and e["engine"] in (0, 1) for e in entries.values())
 
 
 def test_pcc_plain_matches_oracle_over_halvings():

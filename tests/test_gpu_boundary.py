@@ -7,6 +7,8 @@
 * sw_bind_device_spins with a torch tensor as the lattice.
 * The batched launch shape (sw_set_batch_grid): results may not depend on it.
 * The border merge's schedule (sw_set_merge_width): neither may it.
+* The persistent batched engine (sw_set_batch_engine): one cooperative launch
+  with grid barriers must give what the phase kernels give.
 * PCC across tiles in 2D, and at the PCC workload's lattice size (2048^2).
 """
 import numpy as np
@@ -192,6 +194,62 @@ def test_merge_width_does_not_change_results(mode, width):
                 if spec.get("pcc"):
                     perc, pv = lat.pcc_trace(r)
                     assert np.array_equal(perc, ref["perc"]) and np.array_equal(pv, ref["p_trace"]), tag
+
+
+@pytest.mark.parametrize("per_cu", [0, 1])
+def test_persistent_engine_matches_oracle(per_cu):
+    """Every replica of the mix (2D and 3D, ragged, PCC among them) through the
+    persistent engine, in both tile-shape pairs, with as many workgroups as fit
+    and with one per CU (each then walks a long chunk of the list), over two
+    calls; then the engine is switched back mid-run."""
+    refs = [_oracle(s, 7) for s in MIX]
+    for shape in range(len(swgpu.tile_shapes(2))):
+        with swgpu.Lattice([_params(s) for s in MIX]) as lat:
+            for r in range(len(MIX)):
+                lat.set_tile_shape(r, shape)
+            lat.set_mode(swgpu.SW_MODE_BATCHED)
+            lat.set_batch_engine(swgpu.SW_ENGINE_PERSISTENT)
+            lat.set_batch_grid(per_cu)
+            lat.sweep(2)
+            lat.sweep(3)
+            engine, grid = lat.batch_engine()
+            assert engine == swgpu.SW_ENGINE_PERSISTENT and grid >= 1
+            if per_cu:
+                assert grid <= 256 * per_cu
+            lat.set_batch_engine(swgpu.SW_ENGINE_GRAPH)
+            lat.sweep(2)
+            for r, spec in enumerate(MIX):
+                ref = refs[r]
+                tag = f"per_cu {per_cu} shape {shape} replica {r}"
+                assert np.array_equal(lat.spins(r), ref["spins"]), tag
+                assert np.array_equal(lat.labels(r), ref["labels"]), tag
+                assert np.array_equal(lat.series(r), ref["series"]), tag
+                if spec.get("pcc"):
+                    perc, pv = lat.pcc_trace(r)
+                    assert np.array_equal(perc, ref["perc"]) and np.array_equal(pv, ref["p_trace"]), tag
+
+
+def test_persistent_engine_long_call():
+    """More sweeps in one call than one persistent launch runs (4096): the call
+    is split into launches, with the series carried across them."""
+    specs = [dict(dim=2, L=20, T=2.3, seed=61), dict(dim=3, L=6, T=4.0, seed=62)]
+    with swgpu.Lattice([_params(s) for s in specs]) as lat:
+        lat.set_mode(swgpu.SW_MODE_BATCHED)
+        lat.set_batch_engine(swgpu.SW_ENGINE_PERSISTENT)
+        lat.sweep(4100)
+        for r, spec in enumerate(specs):
+            ref = _oracle(spec, 4100)
+            assert np.array_equal(lat.spins(r), ref["spins"])
+            assert np.array_equal(lat.series(r), ref["series"])
+
+
+def test_batch_engine_rejects_unknown():
+    with swgpu.Lattice(_params(dict(dim=2, L=16, T=2.0, seed=1))) as lat:
+        for bad in (-1, 2):
+            with pytest.raises(swgpu.SwError) as ei:
+                lat.set_batch_engine(bad)
+            assert ei.value.code == swgpu.SW_EINVAL
+        assert lat.batch_engine() == (swgpu.SW_ENGINE_GRAPH, 0)
 
 
 def test_merge_width_rejects_other_values():
