@@ -383,8 +383,13 @@ def run_pcc(swgpu, workloads, sweeps: int, replicas: int = 64, trace_every: int 
     return out
 
 
-def run_serving(swgpu, workloads, n_jobs: int, budget_gib: float, slots: int, tick: int, rate: float = 50.0):
-    """Open-loop Poisson job stream (rate jobs/s) through the continuous-batching server."""
+def run_serving(swgpu, workloads, n_jobs: int, budget_gib: float, slots: int, tick: int, rate: float = 50.0,
+                deadline: float = 0.0):
+    """Open-loop Poisson job stream (rate jobs/s) through the continuous-batching server.
+
+    With a deadline (seconds of wall time, 0: none), jobs still queued or
+    running then are cancelled and the result says so; latencies are then
+    those of the jobs that finished."""
     import torch
 
     jobs = workloads.serving(n_jobs=n_jobs, rate=rate)
@@ -402,6 +407,14 @@ def run_serving(swgpu, workloads, n_jobs: int, budget_gib: float, slots: int, ti
             ids.append(srv.submit(swgpu.params_from_replica(j.replica), j.sweeps))
             nxt += 1
         active = srv.step()
+        if deadline and time.perf_counter() - wall0 > deadline:
+            cut = 0
+            for jid in ids:
+                if srv.poll(jid) in ("queued", "running"):
+                    srv.cancel(jid)
+                    cut += 1
+            log(f"serving: deadline of {deadline:.0f} s reached, {cut} jobs cancelled, {len(jobs) - nxt} never submitted")
+            break
         if time.perf_counter() - last_log > 10.0:
             last_log = time.perf_counter()
             log(f"serving: {nxt} submitted, {srv.stats()['done']} done, {active} queued or running")
@@ -422,7 +435,9 @@ def run_serving(swgpu, workloads, n_jobs: int, budget_gib: float, slots: int, ti
     def pct(q):
         return lat[min(len(lat) - 1, int(q * len(lat)))] if lat else None
 
-    return {"jobs": n_jobs, "of_stream": 2000, "done": st["done"], "rejected": st["rejected"], "rate_per_s": rate,
+    return {"jobs": n_jobs, "of_stream": 2000, "submitted": nxt, "done": st["done"], "rejected": st["rejected"],
+            "cancelled_at_deadline": len(ids) - st["done"] - st["rejected"], "deadline_s": deadline or None,
+            "rate_per_s": rate,
             "seconds": wall, "site_updates": st["site_updates"], "site_updates_per_s": st["site_updates"] / wall,
             "p50_latency_s": pct(0.5), "p99_latency_s": pct(0.99), "hbm_budget_gib": budget_gib,
             "slots": slots, "sweeps_per_tick": tick}
@@ -489,6 +504,9 @@ def main():
                     help="run the same jobs again with arrivals scaled so that the offered load is this "
                          "fraction of the throughput the first (saturated) run measured")
     ap.add_argument("--serving-tick", type=int, default=25)
+    ap.add_argument("--serving-rate", type=float, default=50.0, help="Poisson arrival rate of the job stream (jobs/s)")
+    ap.add_argument("--serving-deadline", type=float, default=0.0,
+                    help="stop the stream after this many seconds (cancel what is left; 0: run to the end)")
     ap.add_argument("--only", choices=["pcc", "serving", "batched"], default=None,
                     help="run only this workload (its JSON object alone)")
     ap.add_argument("--summarize", metavar="PROF_DIR",
@@ -535,7 +553,8 @@ def main():
             res = run_batched(swgpu, workloads, args.batched_sweeps, args.batched_plain_sweeps)
         else:
             res = {"serving": run_serving(swgpu, workloads, args.serving_jobs, args.serving_budget_gib,
-                                          args.serving_slots, args.serving_tick)}
+                                          args.serving_slots, args.serving_tick, rate=args.serving_rate,
+                                          deadline=args.serving_deadline)}
             if args.serving_load:
                 res["serving_at_load"] = serving_at_load(swgpu, workloads, args, res["serving"])
         print(json.dumps({"only": args.only, **(res if args.only == "serving" else {args.only: res})}), flush=True)
@@ -600,7 +619,8 @@ def main():
     if not args.no_serving:
         log("serving workload ...")
         result["serving"] = run_serving(swgpu, workloads, args.serving_jobs, args.serving_budget_gib,
-                                        args.serving_slots, args.serving_tick)
+                                        args.serving_slots, args.serving_tick, rate=args.serving_rate,
+                                        deadline=args.serving_deadline)
         if args.serving_load:
             result["serving_at_load"] = serving_at_load(swgpu, workloads, args, result["serving"])
     result.update(cpu)

@@ -287,7 +287,7 @@ int sw_autotune(sw_lattice* h, int32_t sweeps, const char* cache_path);
  *               the last sweep
  *   dev_err     NULL, or a device int32 the caller has zeroed: nonzero after
  *               the call completes if a device consistency check failed
- * Every other buffer comes from a static device array of 20 MiB per device
+ * Every other buffer comes from a static device array of 28 MiB per device
  * (held until the process ends), so lattices are limited to N <= 2^21 sites
  * (1448^2, 128^3): larger ones, and a null spin array, give SW_EINVAL before
  * anything is enqueued.  All calls on one device share that array: calls that

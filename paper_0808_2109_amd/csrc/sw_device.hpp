@@ -69,13 +69,22 @@ struct SwRep {
     int8_t* spins;              // N int8 +1/-1; with FLAG_BITPACK ceil(N/32) uint32 words instead,
                                 // site i up iff bit i%32 of word i/32 is set
     uint16_t* lab16;            // N tile-local labels (tile-local index of the cluster's tile root)
-    int32_t* par;               // N global union-find parents (border roots only)
+    int32_t* par;               // FLAG_KEEP: N entries, the cluster root of every border root (K3a -> K3b)
+    uint64_t* dpar;             // the border merge's union-find over the border roots, which
+                                // hold the slots [t * 2ft, t * 2ft + nb_t) of their tile t in
+                                // rank order; an entry is (parent's site << 32 | parent's slot)
+                                // and a root's names itself (not with FLAG_WIND)
     uint64_t* par64;            // FLAG_WIND: N entries (parent | sheet offsets << 32) of the border
-                                // merge's union-find, which then replaces par until K3a
-    int32_t* lab32;             // N final labels (FLAG_KEEP or FLAG_PCC), else null
+                                // merge's union-find, which then takes the place of dpar
+    uint16_t* fpre;             // PCC (not FLAG_WIND): ntiles * fbw, border roots before each
+                                // word of the tile's border bitmap (the rank of a border root)
+    uint32_t nslots;            // ntiles * 2 * ft: slots of dpar
+    int32_t* lab32;             // N final labels (FLAG_KEEP), else null
     uint32_t* xbits;            // ntiles * xwords crossing-link bits
     uint32_t* fbits;            // ntiles * fbw: border roots of each tile (bit per tile-local site)
-    uint16_t* face;             // ntiles * 2 * ft: labels of the near, then the far face sites
+    uint16_t* face;             // ntiles * 2 * ft: near, then far face sites: the rank of the site's
+                                // tile root among the tile's border roots (FLAG_WIND: the tile-local
+                                // label itself)
     uint32_t* bflip;            // ntiles * fbw: flip bit of every tile-local root (K3a -> K3b)
     int64_t* series;            // 2 * series_cap
     int64_t* acc;               // 2 scratch accumulators (measure)
@@ -257,80 +266,16 @@ __device__ __forceinline__ void lds_join(int* par, int a, int b)
     if (b0 != lo) lds_store(&par[b0], lo);
 }
 
-__device__ __forceinline__ int g_load(const int* p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void g_store(int* p, int v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// parents are checked against [0, x]: a value outside it can only come from a
-// broken invariant; it is reported and the chase stops (returns -1)
-__device__ __forceinline__ int g_find(const SwRep& R, int* par, int x)
-{
-    while (true) {
-        const int p = g_load(&par[x]);
-        if (p == x) return x;
-        if (p < 0 || p > x) {
-            flag_error(R, ERR_PARENT);
-            return -1;
-        }
-        const int gp = g_load(&par[p]);
-        if (gp == p) return p;
-        if (gp < 0 || gp > p) {
-            flag_error(R, ERR_PARENT);
-            return -1;
-        }
-        g_store(&par[x], gp);
-        x = gp;
-    }
-}
-
-__device__ __forceinline__ void g_unite(const SwRep& R, int* par, int a, int b)
-{
-    while (true) {
-        a = g_find(R, par, a);
-        b = g_find(R, par, b);
-        if (a < 0 || b < 0) return;
-        if (a == b) return;
-        if (a > b) {
-            const int t = a;
-            a = b;
-            b = t;
-        }
-        const int old = __hip_atomic_fetch_min(&par[b], a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == b) return;
-        b = old;
-    }
-}
-
-// the parent of x in the border merge's union-find (the 64-bit entries of the
-// winding mode hold it in their low word)
+// the parent of x in the topological rule's union-find (the low word of its
+// 64-bit entry)
 __device__ __forceinline__ int gpar(const SwRep& R, uint32_t x)
 {
-    return (R.flags & FLAG_WIND) ? (int)(uint32_t)R.par64[x] : R.par[x];
+    return (int)(uint32_t)R.par64[x];
 }
 
-// read-only find, for phases that run after all unions are complete
-__device__ __forceinline__ uint32_t ro_find(const SwRep& R, uint32_t x)
-{
-    int p = gpar(R, x);
-    while ((uint32_t)p != x) {
-        if (p < 0 || (uint32_t)p > x) {
-            flag_error(R, ERR_PARENT);
-            return x;
-        }
-        x = (uint32_t)p;
-        p = gpar(R, x);
-    }
-    return x;
-}
-
-// ro_find of a and b, the two chains walked together (one round trip per
-// step of the longer one)
+// read-only find of the roots of a and b in the topological rule's
+// union-find (after all unions), the two chains walked together (one round
+// trip per step of the longer one)
 __device__ __forceinline__ void ro_find2(const SwRep& R, uint32_t& a, uint32_t& b)
 {
     int pa = gpar(R, a), pb = gpar(R, b);
@@ -347,6 +292,110 @@ __device__ __forceinline__ void ro_find2(const SwRep& R, uint32_t& a, uint32_t& 
 }
 
 // --------------------------------------------------------------------------
+// The border merge's union-find over slots.  Only border roots take part in
+// the merge, so each tile gives its border roots consecutive slots (rank
+// order in the tile's border bitmap) and the forest lives in a dense array a
+// few entries per tile long, instead of at scattered site indices.  An entry
+// holds the parent's site index in its high word and the parent's slot in
+// its low word; a root's entry names itself.  Hook-to-min on the site index
+// (the high word decides a 64-bit atomic min) keeps the smallest site of a
+// cluster as its root, as with site-indexed parents.
+// --------------------------------------------------------------------------
+constexpr uint64_t kBrokenEntry = ~0ull;
+
+__device__ __forceinline__ uint64_t pack_node(uint32_t site, uint32_t slot)
+{
+    return ((uint64_t)site << 32) | (uint64_t)slot;
+}
+
+__device__ __forceinline__ uint64_t d_load(const uint64_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// root entry of slot s (whose site is x, or ~0u when unknown) with path
+// halving; parents are checked to lie in range and to have smaller sites
+__device__ __forceinline__ uint64_t d_find(const SwRep& R, uint32_t s, uint32_t x)
+{
+    uint64_t* D = R.dpar;
+    while (true) {
+        const uint64_t e = d_load(&D[s]);
+        const uint32_t ps = (uint32_t)e, px = (uint32_t)(e >> 32);
+        if (ps == s) return e;
+        if (ps >= R.nslots || px >= x) {
+            flag_error(R, ERR_PARENT);
+            return kBrokenEntry;
+        }
+        const uint64_t f = d_load(&D[ps]);
+        const uint32_t gs = (uint32_t)f, gx = (uint32_t)(f >> 32);
+        if (gs == ps) return f;
+        if (gs >= R.nslots || gx >= px) {
+            flag_error(R, ERR_PARENT);
+            return kBrokenEntry;
+        }
+        __hip_atomic_store(&D[s], f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);   // s skips to its grandparent
+        s = gs;
+        x = gx;
+    }
+}
+
+__device__ __forceinline__ void d_unite(const SwRep& R, uint32_t sa, uint32_t xa, uint32_t sb, uint32_t xb)
+{
+    while (true) {
+        const uint64_t ra = d_find(R, sa, xa), rb = d_find(R, sb, xb);
+        if (ra == kBrokenEntry || rb == kBrokenEntry || ra == rb) return;
+        const uint64_t lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
+        const uint64_t old = __hip_atomic_fetch_min(&R.dpar[(uint32_t)hi], lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == hi) return;
+        // hi had been hooked to `old` meanwhile: join that one with lo instead
+        sa = (uint32_t)old;
+        xa = (uint32_t)(old >> 32);
+        sb = (uint32_t)lo;
+        xb = (uint32_t)(lo >> 32);
+    }
+}
+
+// read-only find of the cluster root's site, for phases after all unions;
+// x is the site of slot s
+__device__ __forceinline__ uint32_t d_ro_find(const SwRep& R, uint32_t s, uint32_t x)
+{
+    uint64_t e = d_load(&R.dpar[s]);
+    while ((uint32_t)e != s) {
+        const uint32_t ps = (uint32_t)e, px = (uint32_t)(e >> 32);
+        if (ps >= R.nslots || px >= x) {
+            flag_error(R, ERR_PARENT);
+            return x;
+        }
+        s = ps;
+        x = px;
+        e = d_load(&R.dpar[s]);
+    }
+    return (uint32_t)(e >> 32);
+}
+
+// d_ro_find of two slots, their chains walked together
+__device__ __forceinline__ void d_ro_find2(const SwRep& R, uint32_t sa, uint32_t& xa, uint32_t sb, uint32_t& xb)
+{
+    uint64_t ea = d_load(&R.dpar[sa]), eb = d_load(&R.dpar[sb]);
+    while ((uint32_t)ea != sa || (uint32_t)eb != sb) {
+        const uint32_t pa = (uint32_t)ea, pb = (uint32_t)eb;
+        const uint32_t qa = (uint32_t)(ea >> 32), qb = (uint32_t)(eb >> 32);
+        if (pa >= R.nslots || pb >= R.nslots || (pa != sa && qa >= xa) || (pb != sb && qb >= xb)) {
+            flag_error(R, ERR_PARENT);
+            return;
+        }
+        sa = pa;
+        xa = qa;
+        sb = pb;
+        xb = qb;
+        ea = d_load(&R.dpar[sa]);
+        eb = d_load(&R.dpar[sb]);
+    }
+    xa = (uint32_t)(ea >> 32);
+    xb = (uint32_t)(eb >> 32);
+}
+
+// --------------------------------------------------------------------------
 // Union-find with sheet offsets, for the topological rule of Sec. III (a
 // cluster winds around the periodic box).  Every site of a tile-local
 // cluster lies on one sheet of the box's unwrapped cover (no link inside a
@@ -356,7 +405,7 @@ __device__ __forceinline__ void ro_find2(const SwRep& R, uint32_t& a, uint32_t& 
 // the box's last tile along axis d wraps: it moves one sheet along d.  A link
 // between two sites already in one set whose sheets disagree with the link
 // closes a loop around the box: the cluster winds.  Hooks (larger root under
-// the smaller, as in g_unite) are compare-and-swaps of a root's whole entry;
+// the smaller, as in d_unite) are compare-and-swaps of a root's whole entry;
 // path halving stores composed offsets, which stay valid because an entry
 // only ever relates a node to one of its ancestors.
 // --------------------------------------------------------------------------
@@ -563,7 +612,6 @@ struct K1Cov<C, true> {
     static constexpr int CAP = 2 * C::FT;   // a border root has a site on a near face or a far-face link
     unsigned long long a[CAP];
     unsigned long long b[CAP];
-    int32_t pre[C::FBW];                    // border roots before each bitmap word
 };
 
 template <class C, bool PCC>
@@ -573,7 +621,13 @@ struct alignas(16) K1Smem {
     uint64_t S[C::NR];     // spin-up masks of the rows
     uint64_t SS[C::NR];    // run starts of the rows
     uint32_t XF[2];        // open links leaving through the far x face (bit = row)
-    uint32_t ring[kBlock / 64][kRing];   // per-wave queue of pending unions
+    union {
+        uint32_t ring[kBlock / 64][kRing];   // step 3: per-wave queue of pending unions
+        struct {
+            int32_t pre[C::FBW];                   // border roots before each word of FB (their ranks)
+            alignas(16) uint16_t fst[2 * C::FT];   // tile-local labels of the near, then the far face sites
+        };
+    };
     K1Cov<C, PCC> cov;
 };
 
@@ -932,8 +986,8 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
     }
     wave_lds_sync();   // the run start before xp is a thread of the same row, so of this wave
     if (partok) {
-        uint16_t* nearf = R.face + (size_t)t * (2 * C::FT);
-        uint16_t* farf = nearf + C::FT;
+        uint16_t* nearf = sm.fst;   // staged: they go out as ranks once the border roots are known
+        uint16_t* farf = sm.fst + C::FT;
         const bool nearrow = ly == 0 || (C::D == 3 && lz == 0);
         uint64_t cross = 0;                                   // open links leaving through the far y / z faces
         if (edgeY) cross |= opn[1];
@@ -1017,6 +1071,57 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
     }
     __syncthreads();
 
+    // 4a) ranks of the border roots (border roots before each bitmap word), and
+    //     the face labels out as the ranks of their tile roots: the border
+    //     merge then addresses the union-find slots directly.  With the
+    //     topological rule the labels themselves go out.
+    if (tid < 64) {
+        constexpr int WPL = (C::FBW + 63) / 64;         // bitmap words per lane of wave 0
+        int cnt[WPL];
+        int tot = 0;
+#pragma unroll
+        for (int k = 0; k < WPL; ++k) {
+            const int w = tid * WPL + k;
+            cnt[k] = (w < C::FBW) ? __popc(sm.FB[w]) : 0;
+            tot += cnt[k];
+        }
+        int inc = tot;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(inc, off, 64);
+            if (tid >= off) inc += v;
+        }
+        int ex = inc - tot;
+#pragma unroll
+        for (int k = 0; k < WPL; ++k) {
+            const int w = tid * WPL + k;
+            if (w < C::FBW) sm.pre[w] = ex;
+            ex += cnt[k];
+        }
+    }
+    __syncthreads();
+    {
+        const bool ranks = !(R.flags & FLAG_WIND);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(R.face + (size_t)t * (2 * C::FT));
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(sm.fst);
+        for (int i = tid; i < C::FT; i += blockDim.x) {   // two face sites per thread and step
+            uint32_t w = src[i];
+            if (ranks) {
+                uint32_t o = 0;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const uint32_t v = (w >> (16 * h)) & 0xFFFFu;
+                    // entries of sites outside a ragged tile are never read: any value will do
+                    const uint32_t rk = (v < (uint32_t)C::TS)
+                                            ? (uint32_t)sm.pre[v >> 5] + __popc(sm.FB[v >> 5] & ((1u << (v & 31u)) - 1u))
+                                            : 0xFFFFu;
+                    o |= rk << (16 * h);
+                }
+                w = o;
+            }
+            dst[i] = w;
+        }
+    }
+
     // 4b) PCC: the columns and rows each border cluster occupies in the tile.
     //    A cluster that covers every coordinate of an axis meets the
     //    hyperplane x_a = 0 and so touches a near face of some tile: only
@@ -1027,30 +1132,6 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
     // holds a PCC replica: only PCC replicas have coverage entries)
     if constexpr (PCC) if ((R.flags & (FLAG_PCC | FLAG_WIND)) == FLAG_PCC) {
         using CV = K1Cov<C, true>;
-        constexpr int WPL = (C::FBW + 63) / 64;         // bitmap words per lane of wave 0
-        if (tid < 64) {
-            int cnt[WPL];
-            int tot = 0;
-#pragma unroll
-            for (int k = 0; k < WPL; ++k) {
-                const int w = tid * WPL + k;
-                cnt[k] = (w < C::FBW) ? __popc(sm.FB[w]) : 0;
-                tot += cnt[k];
-            }
-            int inc = tot;
-            for (int off = 1; off < 64; off <<= 1) {
-                const int v = __shfl_up(inc, off, 64);
-                if (tid >= off) inc += v;
-            }
-            int ex = inc - tot;
-#pragma unroll
-            for (int k = 0; k < WPL; ++k) {
-                const int w = tid * WPL + k;
-                if (w < C::FBW) sm.cov.pre[w] = ex;
-                ex += cnt[k];
-            }
-        }
-        __syncthreads();
         if (partok) {
             const unsigned long long rowb = (C::D == 3) ? ((1ull << ly) | (1ull << (C::TY + lz))) : (1ull << ly);
             uint32_t m = ss16;
@@ -1063,7 +1144,7 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
                 const uint32_t root = (uint32_t)lds_load(&sm.par[rowk + x]);   // the walk left the root here
                 const uint32_t fw = sm.FB[root >> 5];
                 if (!((fw >> (root & 31u)) & 1u)) continue;
-                const int rank = sm.cov.pre[root >> 5] + __popc(fw & ((1u << (root & 31u)) - 1u));
+                const int rank = sm.pre[root >> 5] + __popc(fw & ((1u << (root & 31u)) - 1u));
                 if (rank >= CV::CAP) {
                     flag_error(R, ERR_TILE_LABEL);
                     continue;
@@ -1087,7 +1168,7 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
             }
         }
         __syncthreads();
-        const int nb = sm.cov.pre[C::FBW - 1] + __popc(sm.FB[C::FBW - 1]);
+        const int nb = sm.pre[C::FBW - 1] + __popc(sm.FB[C::FBW - 1]);
         unsigned long long* dst = reinterpret_cast<unsigned long long*>(R.cov) + (size_t)t * (2 * CV::CAP);
         for (int k = tid; k < nb && k < CV::CAP; k += blockDim.x) {
             dst[2 * k] = sm.cov.a[k];
@@ -1095,17 +1176,32 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
         }
     }
 
-    // 5) the border bitmap and the far x face's crossing bits; every border
-    //    root starts its own tree in the global union-find
-    for (int w = tid; w < C::FBW; w += blockDim.x) R.fbits[(size_t)t * C::FBW + w] = sm.FB[w];
+    // 5) the border bitmap (and for PCC its ranks) and the far x face's
+    //    crossing bits; every border root starts its own tree in the border
+    //    merge's union-find, at its slot
+    const bool wind = (R.flags & FLAG_WIND) != 0;
+    for (int w = tid; w < C::FBW; w += blockDim.x) {
+        R.fbits[(size_t)t * C::FBW + w] = sm.FB[w];
+        if (R.fpre) R.fpre[(size_t)t * C::FBW + w] = (uint16_t)sm.pre[w];
+    }
+    constexpr int CAP = 2 * C::FT;   // a border root has a site on a near face or a far-face link
+    const uint32_t slot0 = (uint32_t)t * (uint32_t)CAP;
     for (int hw = tid; hw < 2 * C::FBW; hw += blockDim.x) {   // 16 bits per thread
-        uint32_t m = (sm.FB[hw >> 1] >> (16 * (hw & 1))) & 0xFFFFu;
+        const uint32_t word = sm.FB[hw >> 1];
+        uint32_t m = (word >> (16 * (hw & 1))) & 0xFFFFu;
+        int rank = sm.pre[hw >> 1] + ((hw & 1) ? __popc(word & 0xFFFFu) : 0);
         while (m) {
             const int b = __ffs(m) - 1;
             m &= m - 1u;
             const uint32_t gi = local_to_global<C>((uint32_t)(hw * 16 + b), g.x0, g.y0, g.z0, (int)L);
-            if (R.flags & FLAG_WIND) R.par64[gi] = (uint64_t)gi;   // own root, sheet offset 0
-            else R.par[gi] = (int32_t)gi;
+            if (wind) {
+                R.par64[gi] = (uint64_t)gi;   // own root, sheet offset 0
+            } else if (rank < CAP) {
+                R.dpar[slot0 + (uint32_t)rank] = pack_node(gi, slot0 + (uint32_t)rank);
+            } else {
+                flag_error(R, ERR_TILE_LABEL);
+            }
+            ++rank;
         }
     }
     if (tid < C::W0) R.xbits[(size_t)t * C::XW + tid] = sm.XF[tid];
@@ -1230,11 +1326,15 @@ __device__ void k2_tile(const SwRep& R, int t, K2Smem<C>& sm)
             lb[k] = R.face[(size_t)tn * (2 * C::FT) + f];
         }
     }
-    // 2) the first link of each (face, near label, far label) triple
+    // 2) the first link of each (face, near label, far label) triple; the
+    //    labels are the ranks of the two tile roots among their tiles' border
+    //    roots (with the topological rule, the tile-local labels)
+    const bool wind = (R.flags & FLAG_WIND) != 0;
+    const uint32_t lim = wind ? (uint32_t)C::TS : (uint32_t)(2 * C::FT);
 #pragma unroll
     for (int k = 0; k < K::KF; ++k) {
         if (!open[k]) continue;
-        if (la[k] >= (uint32_t)C::TS || lb[k] >= (uint32_t)C::TS) {
+        if (la[k] >= lim || lb[k] >= lim) {
             flag_error(R, ERR_TILE_LABEL);
             continue;
         }
@@ -1252,20 +1352,24 @@ __device__ void k2_tile(const SwRep& R, int t, K2Smem<C>& sm)
         if (d == 0) jx = (ix + 1 == R.ntx) ? 0 : ix + 1;
         else if (d == 1) jy = (iy + 1 == R.nty) ? 0 : iy + 1;
         else jz = (iz + 1 == R.ntz) ? 0 : iz + 1;
+        const int tn = jx + R.ntx * (jy + R.nty * jz);
+        if (!wind) {
+            constexpr uint32_t CAP = 2 * C::FT;
+            d_unite(R, (uint32_t)t * CAP + la0, ~0u, (uint32_t)tn * CAP + lb0, ~0u);
+            continue;
+        }
         const uint32_t ra = tile_site_global<C>(R, ix, iy, iz, la0);
         const uint32_t rb = tile_site_global<C>(R, jx, jy, jz, lb0);
         if (ra >= R.N || rb >= R.N) {
             flag_error(R, ERR_TILE_LABEL);
             continue;
         }
-        if (R.flags & FLAG_WIND) {
+        {
             // the link leaves the box's last tile along d: it wraps
             const bool wraps = (d == 0) ? ix + 1 == R.ntx : (d == 1) ? iy + 1 == R.nty : iz + 1 == R.ntz;
             Sheet w{{0, 0, 0}};
             if (wraps) w.v[d] = 1;
             g_unite64(R, ra, rb, w);
-        } else {
-            g_unite(R, R.par, (int)ra, (int)rb);
         }
     }
     __syncthreads();
@@ -1459,13 +1563,16 @@ __device__ void k3a_tile(const SwRep& R, int t, uint32_t s, K3aSmem<C>& sm, CovA
         }
         root[0] = gi[0];
         root[1] = gi[1];
-        ro_find2(R, root[0], root[1]);
+        if (R.flags & FLAG_WIND) {
+            ro_find2(R, root[0], root[1]);
+        } else {
+            const uint32_t slot0 = (uint32_t)t * (uint32_t)CAP;   // list entry i holds slot t * CAP + i
+            d_ro_find2(R, slot0 + (uint32_t)i, root[0], slot0 + (uint32_t)(two ? i + 64 : i), root[1]);
+        }
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             if (e == 1 && !two) break;
-            // (in winding mode K1 set up only the 64-bit entries, so a root
-            // that is its own cluster's root is written too)
-            if (keep && (root[e] != gi[e] || (R.flags & FLAG_WIND))) R.par[gi[e]] = (int32_t)root[e];
+            if (keep) R.par[gi[e]] = (int32_t)root[e];
             if (flip_bit(root[e], s, k0, k1)) atomicOr(&sm.BF[lr[e] >> 5], 1u << (lr[e] & 31u));
             sm.root[i + 64 * e] = root[e];
         }
@@ -1764,7 +1871,15 @@ __device__ void k_cand_tile(const SwRep& R, int t, uint32_t s)
             const uint32_t v = R.lab16[gi];
             uint32_t r = tile_root_of<C>(R, gi, v);
             if (r == 0xFFFFFFFFu) continue;
-            if ((R.fbits[(size_t)t * C::FBW + (v >> 5)] >> (v & 31u)) & 1u) r = ro_find(R, r);
+            const uint32_t fw = R.fbits[(size_t)t * C::FBW + (v >> 5)];
+            if ((fw >> (v & 31u)) & 1u) {   // a border root: its cluster's root through its slot
+                const uint32_t rank = (uint32_t)R.fpre[(size_t)t * C::FBW + (v >> 5)] + __popc(fw & ((1u << (v & 31u)) - 1u));
+                if (rank >= (uint32_t)(2 * C::FT)) {
+                    flag_error(R, ERR_TILE_LABEL);
+                    continue;
+                }
+                r = d_ro_find(R, (uint32_t)t * (uint32_t)(2 * C::FT) + rank, r);
+            }
             // in-plane position
             uint32_t slot;
             if (C::D == 2) slot = (a == 0) ? (uint32_t)y : (uint32_t)x;

@@ -27,9 +27,10 @@
 
 namespace sw {
 
-// 20 MiB: room for every lattice of up to 2^21 sites (1448^2 in 2D, 128^3 in
-// 3D) in the default tile shapes, ragged tiles and alignment included
-constexpr size_t kScratchBytes = 20u << 20;
+// 28 MiB: room for every lattice of up to 2^21 sites (1448^2 in 2D, 128^3 in
+// 3D) in the default tile shapes, final labels, ragged tiles and alignment
+// included (128^3 with labels takes about 24 MB)
+constexpr size_t kScratchBytes = 28u << 20;
 constexpr uint64_t kNoallocMaxSites = 1ull << 21;
 
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
@@ -67,8 +68,9 @@ __global__ void kzero_i64_kernel(int64_t* p, int64_t n)
 static size_t align256(size_t b) { return (b + 255u) & ~(size_t)255u; }
 
 // carve the descriptor and the per-sweep buffers of h out of base; returns the
-// bytes used (the buffers are placed only when base is not null)
-static size_t carve(SwRep& h, unsigned char* base, SwRep** desc)
+// bytes used (the buffers are placed only when base is not null).  The
+// border roots' cluster roots (par) are needed only when labels are written.
+static size_t carve(SwRep& h, unsigned char* base, SwRep** desc, bool labels)
 {
     const size_t n = h.N, nt = (size_t)h.ntiles;
     size_t off = 0;
@@ -79,7 +81,9 @@ static size_t carve(SwRep& h, unsigned char* base, SwRep** desc)
     };
     unsigned char* d = take(sizeof(SwRep));
     h.lab16 = reinterpret_cast<uint16_t*>(take(2 * n));
-    h.par = reinterpret_cast<int32_t*>(take(4 * n));
+    h.par = labels ? reinterpret_cast<int32_t*>(take(4 * n)) : nullptr;
+    h.nslots = (uint32_t)(nt * 2 * (size_t)h.ft);
+    h.dpar = reinterpret_cast<uint64_t*>(take((size_t)h.nslots * 8));
     h.xbits = reinterpret_cast<uint32_t*>(take(nt * (size_t)h.xwords * 4));
     h.fbits = reinterpret_cast<uint32_t*>(take(nt * (size_t)h.fbw * 4));
     h.bflip = reinterpret_cast<uint32_t*>(take(nt * (size_t)h.fbw * 4));
@@ -112,7 +116,7 @@ extern "C" int sw_sweep_noalloc(const sw_params* params, int8_t* dev_spins, uint
     h.L = params->L;
     h.N = (uint32_t)nsites;
     fill_geometry(h, default_shape(h.dim));
-    if (carve(h, nullptr, nullptr) > kScratchBytes)
+    if (carve(h, nullptr, nullptr, dev_labels != nullptr) > kScratchBytes)
         return fail(SW_EINVAL, "lattice needs more than the %zu scratch bytes", kScratchBytes);
     if (n_sweeps == 0) return SW_OK;
     int dev = 0;
@@ -122,7 +126,7 @@ extern "C" int sw_sweep_noalloc(const sw_params* params, int8_t* dev_spins, uint
     rc = scratch_of(dev, &base);
     if (rc) return rc;
     SwRep* d = nullptr;
-    carve(h, base, &d);
+    carve(h, base, &d, dev_labels != nullptr);
     h.spins = dev_spins;
     h.lab32 = dev_labels;
     h.err = dev_err;

@@ -132,12 +132,17 @@ void fill_geometry(SwRep& h, int shape)
 }
 
 // per-tile buffers: crossing bits, border-root bitmaps and their flip bits,
-// face labels, and for PCC the coverage entries of the border roots
-static uint64_t tile_bytes(const SwRep& h, bool pcc)
+// face ranks, the border merge's slots (not with the topological rule), and
+// for PCC the coverage entries of the border roots (and, for the extension
+// rule or the open box, the ranks of the bitmap words)
+static uint64_t tile_bytes(const SwRep& h, uint32_t flags)
 {
     const uint64_t nt = (uint64_t)h.ntiles;
+    const bool pcc = (flags & FLAG_PCC) != 0, wind = (flags & FLAG_WIND) != 0;
     uint64_t b = nt * (uint64_t)h.xwords * 4 + 2 * nt * (uint64_t)h.fbw * 4 + nt * 2 * (uint64_t)h.ft * 2;
+    if (!wind) b += nt * 2 * (uint64_t)h.ft * 8;
     if (pcc) b += nt * 2 * (uint64_t)h.ft * 16;
+    if (pcc && !wind) b += nt * (uint64_t)h.fbw * 2;
     return b;
 }
 
@@ -154,11 +159,14 @@ uint64_t footprint_bytes(const sw_params* p, int shape)
     h.dim = p->dim;
     h.L = p->L;
     fill_geometry(h, shape);
-    uint64_t b = n * (2 + 4);                                // lab16, par
+    uint64_t b = n * 2;                                      // lab16
     b += (p->flags & SW_BITPACK) ? (n + 31) / 32 * 4 : n;    // spins
-    if (p->flags & SW_KEEP_LABELS) b += 4 * n;               // lab32
+    if (p->flags & SW_KEEP_LABELS) b += 8 * n;               // lab32, the border roots' cluster roots
     if (p->flags & SW_PCC_WIND) b += 8 * n;                  // parents with sheet offsets
-    b += tile_bytes(h, (p->flags & SW_PCC) != 0);            // crossing bits, bitmaps, face labels, coverage
+    uint32_t fl = 0;
+    if (p->flags & SW_PCC) fl |= FLAG_PCC;
+    if (p->flags & SW_PCC_WIND) fl |= FLAG_WIND;
+    b += tile_bytes(h, fl);                                  // crossing bits, bitmaps, face ranks, slots, coverage
     b += 64;                                                 // accumulators
     if (p->flags & SW_PCC) {
         const uint64_t L = (uint64_t)p->L;
@@ -194,28 +202,37 @@ static void dfree(void* p)
     if (p) (void)hipFree(p);
 }
 
+static void free_tile_buffers(SwRep& h)
+{
+    dfree(h.xbits);
+    dfree(h.fbits);
+    dfree(h.bflip);
+    dfree(h.face);
+    dfree(h.dpar);
+    dfree(h.cov);
+    dfree(h.fpre);
+    h.xbits = h.fbits = h.bflip = nullptr;
+    h.face = h.fpre = nullptr;
+    h.cov = h.dpar = nullptr;
+}
+
 // the per-tile buffers of a descriptor whose geometry and flags are filled in
 static int alloc_tile_buffers(SwRep& h)
 {
     const size_t nt = (size_t)h.ntiles;
+    const bool wind = (h.flags & FLAG_WIND) != 0;
     h.xbits = h.fbits = h.bflip = nullptr;
-    h.face = nullptr;
-    h.cov = nullptr;
+    h.face = h.fpre = nullptr;
+    h.cov = h.dpar = nullptr;
+    h.nslots = (uint32_t)(nt * 2 * (size_t)h.ft);
     int rc = dmalloc((void**)&h.xbits, nt * h.xwords * 4, "crossing bits");
     if (!rc) rc = dmalloc((void**)&h.fbits, nt * h.fbw * 4, "border bitmaps");
     if (!rc) rc = dmalloc((void**)&h.bflip, nt * h.fbw * 4, "border flip bits");
-    if (!rc) rc = dmalloc((void**)&h.face, nt * 2 * h.ft * 2, "face labels");
+    if (!rc) rc = dmalloc((void**)&h.face, nt * 2 * h.ft * 2, "face ranks");
+    if (!rc && !wind) rc = dmalloc((void**)&h.dpar, (size_t)h.nslots * 8, "border-merge slots");
     if (!rc && (h.flags & FLAG_PCC)) rc = dmalloc((void**)&h.cov, nt * 2 * h.ft * 16, "coverage entries");
-    if (rc) {
-        dfree(h.xbits);
-        dfree(h.fbits);
-        dfree(h.bflip);
-        dfree(h.face);
-        dfree(h.cov);
-        h.xbits = h.fbits = h.bflip = nullptr;
-        h.face = nullptr;
-        h.cov = nullptr;
-    }
+    if (!rc && (h.flags & FLAG_PCC) && !wind) rc = dmalloc((void**)&h.fpre, nt * h.fbw * 2, "border-root ranks");
+    if (rc) free_tile_buffers(h);
     return rc;
 }
 
@@ -226,11 +243,7 @@ void replica_free(ReplicaH& r)
     dfree(r.h.par);
     dfree(r.h.par64);
     dfree(r.h.lab32);
-    dfree(r.h.xbits);
-    dfree(r.h.fbits);
-    dfree(r.h.bflip);
-    dfree(r.h.face);
-    dfree(r.h.cov);
+    free_tile_buffers(r.h);
     dfree(r.h.series);
     dfree(r.h.acc);
     dfree(r.h.cand);
@@ -242,11 +255,9 @@ void replica_free(ReplicaH& r)
     r.h.lab16 = nullptr;
     r.h.par = r.h.lab32 = r.h.pflag = r.h.perc_trace = nullptr;
     r.h.par64 = nullptr;
-    r.h.xbits = r.h.fbits = r.h.bflip = r.h.bmp = nullptr;
-    r.h.face = nullptr;
+    r.h.bmp = nullptr;
     r.h.series = r.h.acc = nullptr;
     r.h.cand = nullptr;
-    r.h.cov = nullptr;
     r.h.p_trace = nullptr;
 }
 
@@ -280,11 +291,12 @@ int replica_alloc(ReplicaH& r, const sw_params* p, int shape, hipStream_t stream
     r.own_spins = true;
     if ((rc = dmalloc((void**)&h.spins, spin_bytes(h), "spins"))) goto bad;
     if ((rc = dmalloc((void**)&h.lab16, 2 * n, "tile labels"))) goto bad;
-    if ((rc = dmalloc((void**)&h.par, 4 * n, "union-find parents"))) goto bad;
     if (h.flags & FLAG_WIND)
         if ((rc = dmalloc((void**)&h.par64, 8 * n, "union-find parents with sheet offsets"))) goto bad;
-    if (h.flags & FLAG_KEEP)
+    if (h.flags & FLAG_KEEP) {
+        if ((rc = dmalloc((void**)&h.par, 4 * n, "cluster roots of the border roots"))) goto bad;
         if ((rc = dmalloc((void**)&h.lab32, 4 * n, "labels"))) goto bad;
+    }
     if ((rc = alloc_tile_buffers(h))) goto bad;
     if ((rc = dmalloc((void**)&h.acc, 64, "accumulators"))) goto bad;
     if (h.flags & FLAG_SERIES) {
@@ -1107,11 +1119,7 @@ int sw_set_tile_shape(sw_lattice* h, int32_t replica, int32_t shape)
     fill_geometry(probe, shape);
     rc = alloc_tile_buffers(probe);
     if (rc) return rc;
-    dfree(r.h.xbits);
-    dfree(r.h.fbits);
-    dfree(r.h.bflip);
-    dfree(r.h.face);
-    dfree(r.h.cov);
+    free_tile_buffers(r.h);
     r.h = probe;
     h->items_dirty = true;
     return push_desc(h, replica);

@@ -62,7 +62,11 @@ def test_binding_loads_and_validates_without_device(lib_path):
     # footprint is a pure host computation
     p = swgpu.make_params(2, 8192)
     fp = swgpu.Server.footprint(p)
-    assert 7 * 8192 * 8192 <= fp < 8 * 8192 * 8192
+    # spins 1 B, tile labels 2 B, border-merge slots, bitmaps and face ranks
+    # under 1 B per site; kept labels add 8 B per site (labels and the border
+    # roots' cluster roots)
+    assert 3 * 8192 * 8192 <= fp < 4 * 8192 * 8192
+    assert swgpu.Server.footprint(swgpu.make_params(2, 8192, keep_labels=True)) == fp + 8 * 8192 * 8192
     with pytest.raises(swgpu.SwError):
         swgpu.Server.footprint(swgpu.make_params(5, 8))
 
