@@ -262,6 +262,64 @@ def summarize_profiles(prof_dir: str, out_dir: str, trace_cmd: str, pmc_cmd: str
                                   ("_kernel_trace.txt", "_hbm_traffic.txt", "_traffic_pmc.json")]}))
 
 
+SQ_ORDER = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM", "SQ_INSTS_BRANCH",
+            "SQ_ACTIVE_INST_VALU", "SQ_THREAD_CYCLES_VALU", "SQ_ACTIVE_INST_LDS", "SQ_LDS_IDX_ACTIVE",
+            "SQ_LDS_BANK_CONFLICT", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY",
+            "SQ_ACTIVE_INST_ANY")
+
+
+def summarize_sq(prof_dir: str, out_dir: str, cmd_a: str, cmd_b: str):
+    """SQ counters of the plain path's kernels (last dispatch of each) from two
+    rocprofv3 --pmc passes under prof_dir/sq_a and prof_dir/sq_b."""
+    import collections
+
+    cols = collections.OrderedDict()    # column title -> {counter: value}
+    durs = collections.defaultdict(list)
+    for sub in ("sq_a", "sq_b"):
+        q = ("select k.dispatch_id, k.name, k.duration, p.counter_name, p.counter_value from pmc_events p "
+             "join kernels k on p.dispatch_id = k.dispatch_id")
+        last = {}                           # column -> dispatch id of its last launch
+        vals = collections.defaultdict(lambda: collections.defaultdict(float))
+        info = {}
+        for did, name, dur, cname, val in _db_rows(os.path.join(prof_dir, sub), q):
+            k = _kernel_of(name)
+            if not k:
+                continue
+            key, tag, _ = k
+            col = f"{key} {tag}"
+            vals[did][cname] += val
+            info[did] = (col, dur)
+            if did > last.get(col, -1):
+                last[col] = did
+        for col, did in sorted(last.items()):
+            cols.setdefault(col, {}).update(vals[did])
+            durs[col].append(info[did][1] / 1e3)
+    names = list(cols)
+    lines = ["# rocprofv3 SQ counters, plain sweep workload (8192^2 at T_c + 256^3 at T=4.5115), last dispatch of each kernel",
+             "# commands (two passes, at most 8 SQ counters each):", f"#   {cmd_a}", f"#   {cmd_b}",
+             "# counter values are summed over the counter's instances", "#",
+             "# " + f"{'counter':26s}" + "".join(f"{n:>22s}" for n in names)]
+    for c in SQ_ORDER:
+        if any(c in cols[n] for n in names):
+            lines.append("  " + f"{c:26s}" + "".join(f"{cols[n].get(c, float('nan')):22.0f}" for n in names))
+    lines.append("  " + f"{'duration_us (pass a, b)':26s}" +
+                 "".join(f"{' / '.join(f'{d:.1f}' for d in durs[n]):>22s}" for n in names))
+    lines += ["#", "# derived (per kernel):"]
+    for n in names:
+        v = cols[n]
+        w = v.get("SQ_WAVES", 0.0) or float("nan")
+        lanes = v.get("SQ_THREAD_CYCLES_VALU", 0.0) / (v.get("SQ_ACTIVE_INST_VALU", 0.0) or float("nan"))
+        confl = v.get("SQ_LDS_BANK_CONFLICT", 0.0) / (v.get("SQ_LDS_IDX_ACTIVE", 0.0) or float("nan"))
+        lines.append(f"#   {n}: VALU instructions per wave {v.get('SQ_INSTS_VALU', 0) / w:.0f}, "
+                     f"SALU {v.get('SQ_INSTS_SALU', 0) / w:.0f}, LDS {v.get('SQ_INSTS_LDS', 0) / w:.0f}, "
+                     f"VMEM {v.get('SQ_INSTS_VMEM', 0) / w:.0f}; active lanes per VALU instruction {lanes:.1f} of 64; "
+                     f"LDS bank-conflict cycles / LDS active cycles {confl:.2f}")
+    path = os.path.join(out_dir, PROFILE_PREFIX + "_sq_counters.txt")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(json.dumps({"written": [path]}))
+
+
 COPY_PROBE_BYTES = 256 << 20
 
 
@@ -512,10 +570,14 @@ def main():
     ap.add_argument("--summarize", metavar="PROF_DIR",
                     help="write the profiles/ summaries from rocprofv3 runs under PROF_DIR (no GPU needed)")
     ap.add_argument("--summary-commands", nargs=3, metavar=("TRACE", "PMC", "COPY"), default=("?", "?", "?"))
+    ap.add_argument("--sq-commands", nargs=2, metavar=("PASS_A", "PASS_B"), default=None,
+                    help="with --summarize: also summarise the SQ counter passes under PROF_DIR/sq_a, sq_b")
     args = ap.parse_args()
 
     if args.summarize:
         summarize_profiles(args.summarize, os.path.join(ROOT, "profiles"), *args.summary_commands)
+        if args.sq_commands:
+            summarize_sq(args.summarize, os.path.join(ROOT, "profiles"), *args.sq_commands)
         return
 
     if args.gpus != 1:
