@@ -235,8 +235,9 @@ int sw_set_spins(sw_lattice* h, int32_t replica, const int8_t* host_buf, int64_t
 
 /* Use a caller-owned device buffer as the replica's spin array (its contents
  * become the current configuration): N int8 of +1/-1, or for a SW_BITPACK
- * replica ceil(N/32) uint32 words in the packed layout.  The library never
- * frees it; it must stay valid until sw_free or the next bind. */
+ * replica ceil(N/32) uint32 words in the packed layout, 16-byte aligned
+ * (SW_EINVAL otherwise).  The library never frees it; it must stay valid until
+ * sw_free or the next bind. */
 int sw_bind_device_spins(sw_lattice* h, int32_t replica, void* dev_ptr);
 
 /* Enable per-phase kernel timing with HIP events on the handle's stream. */
@@ -279,7 +280,8 @@ int sw_autotune(sw_lattice* h, int32_t sweeps, const char* cache_path);
  *               the other flags are ignored (the outputs below decide)
  *   dev_spins   device array of N int8 +1/-1, x fastest: the configuration
  *               before sweep sweep0 on entry, after sweep sweep0+n_sweeps-1
- *               on return (caller-owned, read and written in place)
+ *               on return (caller-owned, read and written in place,
+ *               16-byte aligned)
  *   sweep0      index of the first sweep (keys the random stream)
  *   dev_series  NULL, or a device array of 2*n_sweeps int64: row k receives
  *               E_int and M after sweep sweep0+k (the call clears it first)
@@ -289,7 +291,7 @@ int sw_autotune(sw_lattice* h, int32_t sweeps, const char* cache_path);
  *               the call completes if a device consistency check failed
  * Every other buffer comes from a static device array of 28 MiB per device
  * (held until the process ends), so lattices are limited to N <= 2^21 sites
- * (1448^2, 128^3): larger ones, and a null spin array, give SW_EINVAL before
+ * (1448^2, 128^3): larger ones, and a null or misaligned spin array, give SW_EINVAL before
  * anything is enqueued.  All calls on one device share that array: calls that
  * overlap on one device (other streams, other threads) race and must be
  * serialised by the caller.  The results equal those of sw_init + sw_set_spins

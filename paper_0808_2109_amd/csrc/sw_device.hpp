@@ -68,7 +68,8 @@ struct SwRep {
     int32_t active;             // batched mode: replica takes part
     int8_t* spins;              // N int8 +1/-1; with FLAG_BITPACK ceil(N/32) uint32 words instead,
                                 // site i up iff bit i%32 of word i/32 is set
-    uint16_t* lab16;            // N tile-local labels (tile-local index of the cluster's tile root)
+    uint16_t* lab16;            // N tile-local labels (tile-local index of the cluster's tile root),
+                                // allocated for N rounded up to a multiple of 4
     int32_t* par;               // FLAG_KEEP: N entries, the cluster root of every border root (K3a -> K3b)
     uint64_t* dpar;             // the border merge's union-find over the border roots, which
                                 // hold the slots [t * 2ft, t * 2ft + nb_t) of their tile t in
@@ -1694,6 +1695,77 @@ __device__ void k3_lean_tile(const SwRep& R, int t, const TileGeo& g, K3Smem<C>&
     __syncthreads();
 }
 
+// K3b when no final labels are asked for and rows are not whole quads of
+// sites (int8 spins).  A tile row's stretch of the spin array then starts
+// anywhere in a 4-byte word: each thread takes one aligned word of a row (a
+// row spans at most TX/4 + 1 of them), loads the four labels under it with
+// one aligned 8-byte load (labels of the neighbouring tile's sites are read
+// and ignored), and stores the word whole when all four sites are the tile's,
+// else only the bytes that are.  The label check is folded as in the lean path.
+template <class C>
+__device__ void k3_word_lean_tile(const SwRep& R, int t, const TileGeo& g, K3Smem<C>& sm)
+{
+    const int tid = threadIdx.x;
+    const uint32_t L = (uint32_t)R.L;
+    constexpr int WR = C::TX / 4 + 1;                     // aligned words a row can touch
+    constexpr int NW = C::NR * WR;
+    constexpr int WPT = (NW + kK3Block - 1) / kK3Block;   // words per thread (blockDim = kK3Block)
+    static_assert((C::TS & (C::TS - 1)) == 0, "a label masked to TS - 1 stays inside the bitmap");
+    uint2 lv[WPT];
+    uint32_t wa[WPT];   // the word's first site
+    uint32_t lo[WPT];   // tile-local index of that site (may be below the row's first: then it wraps)
+    uint32_t inm[WPT];  // bit i: site wa + i belongs to the tile's row
+#pragma unroll
+    for (int j = 0; j < WPT; ++j) {
+        const int q = tid + kK3Block * j;
+        const int r = q / WR, wi = q % WR;
+        const int ly = r % C::TY, lz = r / C::TY;
+        inm[j] = 0u;
+        lv[j] = make_uint2(0u, 0u);
+        wa[j] = 0u;
+        lo[j] = 0u;
+        if (q < NW && ly < g.wy && lz < g.wz) {
+            const uint32_t a0 = (uint32_t)g.x0 + L * ((uint32_t)(g.y0 + ly) + L * (uint32_t)(g.z0 + lz));
+            const uint32_t a1 = a0 + (uint32_t)g.wx;
+            const uint32_t w = (a0 & ~3u) + 4u * (uint32_t)wi;
+            if (w < a1) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (w + (uint32_t)i >= a0 && w + (uint32_t)i < a1) inm[j] |= 1u << i;
+                wa[j] = w;
+                lo[j] = (uint32_t)(r * C::TX) + (w - a0);   // modulo 2^32 when w < a0
+                lv[j] = *reinterpret_cast<const uint2*>(R.lab16 + w);   // the label array holds N rounded up to 4
+            }
+        }
+    }
+    for (int w = tid; w < C::FBW; w += blockDim.x) sm.FL[w] = R.bflip[(size_t)t * C::FBW + w];
+    __syncthreads();
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < WPT; ++j) {
+        if (!inm[j]) continue;
+        uint32_t out = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t lab = (i & 1) ? ((i >> 1) ? lv[j].y : lv[j].x) >> 16 : ((i >> 1) ? lv[j].y : lv[j].x) & 0xFFFFu;
+            const bool mine = (inm[j] >> i) & 1u;
+            bad |= mine && lab > lo[j] + (uint32_t)i;
+            const uint32_t lr = lab & (uint32_t)(C::TS - 1);
+            const uint32_t bit = (sm.FL[lr >> 5] >> (lr & 31u)) & 1u;
+            out |= (bit ? 0x01u : 0xFFu) << (8 * i);
+        }
+        if (inm[j] == 0xFu) {
+            *reinterpret_cast<uint32_t*>(R.spins + wa[j]) = out;
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if ((inm[j] >> i) & 1u) R.spins[wa[j] + (uint32_t)i] = (int8_t)(out >> (8 * i));
+        }
+    }
+    if (bad) flag_error(R, ERR_TILE_LABEL);
+    __syncthreads();
+}
+
 // The new spins of a bit-packed lattice, one site per thread: the bits of one
 // 32-bit word are combined over the wave, and the word is updated with an
 // atomic AND of its cleared bits then an OR of its set bits, so that tiles
@@ -1765,6 +1837,10 @@ __device__ void k3_tile(const SwRep& R, int t, uint32_t s, K3Smem<C>& sm)
     if (!labels && quads && (!packed || (L & 7u) == 0)) {
         if ((L & 7u) == 0) k3_lean_tile<C, 8>(R, t, g, sm);
         else k3_lean_tile<C, 4>(R, t, g, sm);
+        return;
+    }
+    if (!labels && !packed) {   // rows that are not whole quads of sites
+        k3_word_lean_tile<C>(R, t, g, sm);
         return;
     }
     if (packed) {                                        // labels, or rows that are not whole bytes of bits

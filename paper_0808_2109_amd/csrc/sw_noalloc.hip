@@ -80,7 +80,7 @@ static size_t carve(SwRep& h, unsigned char* base, SwRep** desc, bool labels)
         return p;
     };
     unsigned char* d = take(sizeof(SwRep));
-    h.lab16 = reinterpret_cast<uint16_t*>(take(2 * n));
+    h.lab16 = reinterpret_cast<uint16_t*>(take(2 * ((n + 3) & ~(size_t)3)));   // whole groups of 4 sites
     h.par = labels ? reinterpret_cast<int32_t*>(take(4 * n)) : nullptr;
     h.nslots = (uint32_t)(nt * 2 * (size_t)h.ft);
     h.dpar = reinterpret_cast<uint64_t*>(take((size_t)h.nslots * 8));
@@ -104,6 +104,7 @@ extern "C" int sw_sweep_noalloc(const sw_params* params, int8_t* dev_spins, uint
     if (params->flags & (SW_PCC | SW_PCC_WIND)) return fail(SW_EINVAL, "the allocation-free sweep has no PCC feedback");
     if (params->flags & SW_BITPACK) return fail(SW_EINVAL, "the allocation-free sweep takes int8 spins");
     if (!dev_spins) return fail(SW_EINVAL, "null spin array");
+    if (reinterpret_cast<uintptr_t>(dev_spins) & 15u) return fail(SW_EINVAL, "the spin array must be 16-byte aligned");
     if (n_sweeps < 0) return fail(SW_EINVAL, "negative sweep count");
     if ((uint64_t)sweep0 + (uint64_t)n_sweeps > 0xFFFFFFF0ull) return fail(SW_EINVAL, "sweep index overflow");
     const uint64_t nsites = nsites_of(params);

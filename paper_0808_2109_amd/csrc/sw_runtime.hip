@@ -159,7 +159,7 @@ uint64_t footprint_bytes(const sw_params* p, int shape)
     h.dim = p->dim;
     h.L = p->L;
     fill_geometry(h, shape);
-    uint64_t b = n * 2;                                      // lab16
+    uint64_t b = 2 * ((n + 3) & ~(uint64_t)3);              // lab16 (whole groups of 4 sites)
     b += (p->flags & SW_BITPACK) ? (n + 31) / 32 * 4 : n;    // spins
     if (p->flags & SW_KEEP_LABELS) b += 8 * n;               // lab32, the border roots' cluster roots
     if (p->flags & SW_PCC_WIND) b += 8 * n;                  // parents with sheet offsets
@@ -290,7 +290,9 @@ int replica_alloc(ReplicaH& r, const sw_params* p, int shape, hipStream_t stream
     int rc;
     r.own_spins = true;
     if ((rc = dmalloc((void**)&h.spins, spin_bytes(h), "spins"))) goto bad;
-    if ((rc = dmalloc((void**)&h.lab16, 2 * n, "tile labels"))) goto bad;
+    // (rounded up to whole groups of 4 sites: the flip kernel loads 4 labels
+    // from any 4-site-aligned position below N)
+    if ((rc = dmalloc((void**)&h.lab16, 2 * ((n + 3) & ~(size_t)3), "tile labels"))) goto bad;
     if (h.flags & FLAG_WIND)
         if ((rc = dmalloc((void**)&h.par64, 8 * n, "union-find parents with sheet offsets"))) goto bad;
     if (h.flags & FLAG_KEEP) {
@@ -1070,6 +1072,8 @@ int sw_bind_device_spins(sw_lattice* h, int32_t replica, void* dev_ptr)
     int rc = check_rep(h, replica);
     if (rc) return rc;
     if (!dev_ptr) return fail(SW_EINVAL, "null device pointer");
+    if (reinterpret_cast<uintptr_t>(dev_ptr) & 15u)
+        return fail(SW_EINVAL, "the spin array must be 16-byte aligned (the kernels move whole vectors of spins)");
     rc = set_device(h);
     if (!rc) rc = sync_mirror(h);
     if (rc) return rc;

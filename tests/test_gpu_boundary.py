@@ -120,6 +120,16 @@ def test_bind_device_spins_uses_the_torch_tensor(mode):
     assert int(t.abs().sum().item()) == L * L
 
 
+def test_bind_device_spins_refuses_a_misaligned_tensor():
+    L = 40
+    base = torch.ones(L * L + 16, dtype=torch.int8, device="cuda")
+    with swgpu.Lattice(swgpu.make_params(2, L, T=2.3, seed=3)) as lat:
+        with pytest.raises(swgpu.SwError) as ei:
+            lat.bind_device_spins(0, base[1:1 + L * L])       # 1 byte past a 16-byte boundary
+        assert ei.value.code == swgpu.SW_EINVAL
+        lat.bind_device_spins(0, base[16:16 + L * L])         # aligned: accepted
+
+
 MIX = [
     dict(dim=2, L=64, T=2.1, seed=11),
     dict(dim=2, L=100, T=TC, seed=12),

@@ -167,19 +167,23 @@ def test_full_size_first_sweeps(dim, L, T):
 
 
 @pytest.mark.parametrize("dim,L,T", [(2, 100, TC), (2, 36, 2.6), (3, 20, workloads.TC_3D),
-                                     (2, 64, TC), (2, 48, 2.1), (3, 24, 5.0)])
-def test_sweeps_without_labels_or_series(dim, L, T):
+                                     (2, 64, TC), (2, 48, 2.1), (3, 24, 5.0),
+                                     (2, 37, 2.3), (2, 130, TC), (2, 203, 2.4), (3, 13, 4.0), (3, 21, 5.0)])
+@pytest.mark.parametrize("shape", [0, 1])
+def test_sweeps_without_labels_or_series(dim, L, T, shape):
     """Sweeps that keep no labels and record no series (the flip kernel's lean
-    path: groups of 4 sites when L is a multiple of 4 only, of 8 when of 8),
-    ragged tiles included: spins after each of three sweeps."""
+    paths: groups of 8 sites when L is a multiple of 8, of 4 when of 4 only,
+    single sites otherwise), ragged tiles included, in both tile shapes: spins
+    after each of three sweeps."""
     seed = 9
     with swgpu.Lattice(swgpu.make_params(dim, L, T=T, seed=seed)) as lat:
+        lat.set_tile_shape(0, shape)
         thr = lat.state()[2]
         spins = oracle.init_spins(dim, L, seed)
         for k in range(3):
             lat.sweep(1)
             spins, _ = oracle.sweep(dim, L, seed, k, thr, spins)
-            assert np.array_equal(lat.spins(), spins), f"spins differ after sweep {k} (dim={dim} L={L})"
+            assert np.array_equal(lat.spins(), spins), f"spins differ after sweep {k} (dim={dim} L={L} shape={shape})"
 
 
 @pytest.mark.parametrize("dim,L,T,shape", [(2, 8192, TC, 0), (3, 256, workloads.TC_3D, 0),

@@ -72,3 +72,5 @@ def test_noalloc_refuses_what_it_cannot_do():
         assert rc == swgpu.SW_EINVAL
     ok = swgpu.make_params(2, 64, T=2.3, seed=1)
     assert swgpu.lib().sw_sweep_noalloc(ok, None, 0, 1, None, None, None, None) == swgpu.SW_EINVAL
+    # a spin array that is not 16-byte aligned is refused before it is touched
+    assert swgpu.lib().sw_sweep_noalloc(ok, swgpu.ctypes.c_void_p(4097), 0, 1, None, None, None, None) == swgpu.SW_EINVAL
