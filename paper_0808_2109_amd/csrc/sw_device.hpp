@@ -697,37 +697,10 @@ __device__ __forceinline__ uint64_t row_gather(uint32_t part, int q)
     return v;
 }
 
-// open bonds among the n <= 16 links lbase + x whose ends are equal (eq):
-// byte a of Philox(l >> 4, 0, s, BOND) for link l is the high byte of u; a tie
-// with thr >> 24 draws the low 24 bits from REFINE.  The general form, for
-// parts that do not start on a 16-link boundary (L not a multiple of 16).
-__device__ inline uint32_t part_bonds(uint32_t eq, uint32_t lbase, int n, uint32_t s, uint32_t t_hi, uint32_t t_lo,
-                                      uint32_t k0, uint32_t k1)
-{
-    if (!eq) return 0;
-    if (t_hi >= 256u) return eq;                     // P = 1: every equal link is a bond
-    uint32_t op = 0;
-    const uint32_t b0 = lbase >> 4, b1 = (lbase + (uint32_t)n - 1u) >> 4;
-    for (uint32_t blk = b0; blk <= b1; ++blk) {
-        const U4 q = philox10(blk, 0u, s, kTagBond, k0, k1);
-        for (int k = 0; k < 16; ++k) {
-            const int xl = (int)(blk * 16u + (uint32_t)k - lbase);
-            if (xl < 0 || xl >= n || !((eq >> xl) & 1u)) continue;
-            const uint32_t a = (pick(q, (uint32_t)k >> 2) >> (8 * (k & 3))) & 0xFFu;
-            bool open = a < t_hi;
-            if (a == t_hi) {
-                const uint32_t l = blk * 16u + (uint32_t)k;
-                const U4 q2 = philox10(l >> 2, 0u, s, kTagRefine, k0, k1);
-                open = (pick(q2, l & 3u) & 0xFFFFFFu) < t_lo;
-            }
-            if (open) op |= 1u << xl;
-        }
-    }
-    return op;
-}
-
-// First stage of part_bonds for a part of 16 links: the bonds that the high
-// bytes decide, and in `ties` the equal links whose byte equals thr >> 24
+// Bonds of a part of up to 16 links lbase + x whose ends are equal (eq; the
+// bits of links past the part's end are clear): the bonds that the high bytes
+// decide (byte a of Philox(l >> 4, 0, s, BOND) for link l is the high byte of
+// its uniform), and in `ties` the equal links whose byte equals thr >> 24
 // (decided by the REFINE stream; the caller draws those for all directions
 // in one loop, so a wave pays about one refinement call per sweep instead of
 // one per direction).  When the part does not start on a 16-link boundary
@@ -846,12 +819,10 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
         for (int d = 0; d < C::D; ++d) {
             const uint32_t eqp = (uint32_t)(eq[d] >> xp) & 0xFFFFu;
             const uint32_t lbase = (uint32_t)d * N + gi0 + (uint32_t)xp;
-            if (partok && np == 16) {
+            if (partok) {   // (a part cut short by the tile's edge has the bits past its end clear in eq)
                 uint32_t td;
                 bits[d] = part_bonds_coarse(eqp, lbase, s, t_hi, k0, k1, td);
                 ties |= (uint64_t)td << (16 * d);
-            } else if (partok) {
-                bits[d] = part_bonds(eqp, lbase, np, s, t_hi, t_lo, k0, k1);
             }
         }
         while (ties) {
