@@ -664,18 +664,19 @@ __device__ __forceinline__ uint32_t packed_bits(const uint32_t* w, uint32_t pos,
 }
 
 // up bits of the n <= 16 sites from site index i, int8 or bit-packed.  A
-// full part that does not start on a 16-byte boundary is read as the five
-// aligned words around it, cut with byte alignment, when those words lie
-// inside the array.
+// part that does not start on a 16-byte boundary is read as the five aligned
+// words around it, cut with byte alignment, when those words lie inside the
+// array (sites past the part's n are read and masked off).
 __device__ __forceinline__ uint32_t load_spins(const SwRep& R, uint32_t i, int n, bool wide)
 {
     if (R.flags & FLAG_BITPACK) return packed_bits(reinterpret_cast<const uint32_t*>(R.spins), i, n);
-    if (!wide && n == 16 && (i & ~3u) + 20u <= R.N) {
+    if (!wide && (i & ~3u) + 20u <= R.N) {
         const uint32_t* w = reinterpret_cast<const uint32_t*>(R.spins + (i & ~3u));
         const uint32_t sh = i & 3u;
         const uint32_t d0 = w[0], d1 = w[1], d2 = w[2], d3 = w[3], d4 = w[4];
-        return up16(make_uint4(__builtin_amdgcn_alignbyte(d1, d0, sh), __builtin_amdgcn_alignbyte(d2, d1, sh),
-                               __builtin_amdgcn_alignbyte(d3, d2, sh), __builtin_amdgcn_alignbyte(d4, d3, sh)));
+        const uint32_t m = up16(make_uint4(__builtin_amdgcn_alignbyte(d1, d0, sh), __builtin_amdgcn_alignbyte(d2, d1, sh),
+                                           __builtin_amdgcn_alignbyte(d3, d2, sh), __builtin_amdgcn_alignbyte(d4, d3, sh)));
+        return m & (uint32_t)low_bits(n);
     }
     return load_part(R.spins + i, n, wide);
 }
