@@ -53,6 +53,19 @@ def test_noalloc_equals_the_handle_path_on_consecutive_calls():
         assert np.array_equal(got[2], ref["series"])
 
 
+@pytest.mark.parametrize("dim,L,T", [(3, 128, workloads.TC_3D), (2, 1448, workloads.TC_2D)])
+def test_noalloc_at_the_largest_size(dim, L, T):
+    """The largest lattices the static scratch array takes (2^21 sites), with
+    labels and series, then a small one on the leftovers: equal to the handle
+    path bit for bit."""
+    for d, l, t, seed, sweep0, n in ((dim, L, T, 21, 7, 2), (2, 50, 2.4, 22, 0, 2)):
+        start = workloads.random_spins(d, l, 500 + seed)
+        got = _noalloc(d, l, t, seed, start, sweep0, n)
+        want = _handle_path(d, l, t, seed, start, sweep0, n)
+        for g, w, what in zip(got, want, ("spins", "labels", "series")):
+            assert np.array_equal(g, w), f"{what} differ (dim={d} L={l})"
+
+
 def test_noalloc_without_optional_outputs():
     dim, L, T, seed = 2, 128, 2.2, 9
     start = workloads.random_spins(dim, L, 3)
