@@ -66,10 +66,17 @@ SOURCES = ["paper_0808_2109_amd/csrc/sw_device.hpp", "paper_0808_2109_amd/csrc/s
 
 
 def source_hash() -> str:
+    """Hash of the kernel sources' code: comments and blank lines are left
+    out, so that a counter summary stays valid across comment-only edits."""
+    import re
+
     h = hashlib.sha256()
     for s in SOURCES:
-        with open(os.path.join(ROOT, s), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, s)) as f:
+            for line in f:
+                code = re.sub(r"//.*", "", line).strip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

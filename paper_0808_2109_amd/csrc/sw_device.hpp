@@ -7,18 +7,21 @@
 //       draw the bonds of the tile's own links from Philox as bit masks, label
 //       the tile's clusters in LDS (runs along x from the bond masks, a
 //       union-find over the runs of neighbouring rows), write a 16-bit
-//       tile-local label per site, the labels of the tile's face sites, the
-//       bits of the tile's open links that leave it and its border roots.  The
-//       tile plays the part of a domain of Sec. II.
-//   K2  per far-face site: join, in a global union-find over tile-local roots,
-//       the two ends of every open link that leaves a tile (the border
-//       reconciliation of Sec. II, in one pass instead of the master's second
-//       labelling or the iterated neighbour exchange).
+//       tile-local label per site, the bits of the tile's open links that
+//       leave it, its border roots (tile roots of clusters that reach its
+//       faces), each with a slot of the border merge's union-find, and for
+//       every face site the slot rank of its tile root.  The tile plays the
+//       part of a domain of Sec. II.
+//   K2  per far-face site: join, in the global union-find over the border
+//       roots' slots, the two ends of every open link that leaves a tile (the
+//       border reconciliation of Sec. II, in one pass instead of the master's
+//       second labelling or the iterated neighbour exchange).
 //   K3a per tile: find the cluster root of each of the tile's border roots
 //       (the smallest site index of the cluster: the label identity that the
 //       min-label rule of Sec. II.B converges to) and that cluster's flip bit.
 //   K3b per tile: give every site its cluster's new spin (Sec. I step 3).
-// plus the extension-rule percolation test and p feedback of Sec. III.
+// plus the percolation tests and p feedback of Sec. III (extension rule,
+// open-box spanning, topological rule).
 //
 // Every union hooks the larger root under the smaller one, so the final roots
 // do not depend on the order of unions, the tile shape or the schedule: the
@@ -300,7 +303,7 @@ __device__ __forceinline__ void ro_find2(const SwRep& R, uint32_t& a, uint32_t& 
 // holds the parent's site index in its high word and the parent's slot in
 // its low word; a root's entry names itself.  Hook-to-min on the site index
 // (the high word decides a 64-bit atomic min) keeps the smallest site of a
-// cluster as its root, as with site-indexed parents.
+// cluster as its root, the canonical label.
 // --------------------------------------------------------------------------
 constexpr uint64_t kBrokenEntry = ~0ull;
 
