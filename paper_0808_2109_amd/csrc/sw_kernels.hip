@@ -340,7 +340,7 @@ __device__ __forceinline__ void item_range(int nitems, int& i0, int& i1)
 template <class C2, class C3, bool P2, bool P3>
 __device__ __forceinline__ void k1_item(const SwRep* reps, const EngineItem& item, int it, int n_sweeps, char* smem)
 {
-    const SwRep& R = reps[item.rep];
+    const SwRep R = reps[item.rep];   // a private copy: stores to the lattice's arrays cannot alias it
     uint32_t s;
     if (!rep_runs(R, it, n_sweeps, s)) return;
     int64_t* dst = nullptr;
@@ -357,7 +357,7 @@ __device__ __forceinline__ void k1_item(const SwRep* reps, const EngineItem& ite
 template <class C2, class C3, int NT>
 __device__ __forceinline__ void k2_item(const SwRep* reps, const EngineItem& item, int it, int n_sweeps, char* smem)
 {
-    const SwRep& R = reps[item.rep];
+    const SwRep R = reps[item.rep];   // a private copy: stores to the lattice's arrays cannot alias it
     uint32_t s;
     if (!rep_runs(R, it, n_sweeps, s)) return;
     if (R.dim == 2) k2_tile<C2, NT>(R, item.tile, *reinterpret_cast<K2Smem<C2>*>(smem));
@@ -379,7 +379,7 @@ __device__ __forceinline__ void kc_item(const SwRep* reps, const EngineItem& ite
 template <class C2, class C3>
 __device__ __forceinline__ void k3a_item(const SwRep* reps, const EngineItem& item, int it, int n_sweeps, char* smem)
 {
-    const SwRep& R = reps[item.rep];
+    const SwRep R = reps[item.rep];   // a private copy: stores to the lattice's arrays cannot alias it
     uint32_t s;
     if (!rep_runs(R, it, n_sweeps, s)) return;
     wave_lds_sync();   // the previous item's reads of the tables are done
@@ -840,52 +840,97 @@ int launch_set_state(SwRep* d, uint32_t sweep, uint32_t measured, uint32_t first
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
+struct BatchArgs {
+    SwRep* reps;
+    const EngineItem* items;
+    const EngineItem* cand;
+    const EngineItem* perc;
+    int nreps, nitems, ncand, nperc, n_sweeps, any_pcc, ig, k2w;
+    bool loop;
+    hipStream_t stream;
+};
+
+// one sweep's phase launches over the work list for tile configurations CA and
+// CB (2D and 3D); a batch whose replicas all have one dimension passes that
+// dimension's configuration for both, so that the workgroups and the shared
+// memory are sized for it alone
+template <class CA, class CB, bool LP>
+static void batch_phases(const BatchArgs& a, int it)
+{
+    const bool pcc2 = (a.any_pcc & 1) != 0, pcc3 = (a.any_pcc & 2) != 0;   // a 2D / 3D PCC replica is active
+    const bool pa = (CA::D == 2) ? pcc2 : pcc3, pb = (CB::D == 2) ? pcc2 : pcc3;
+    const dim3 g(a.ig), b1(max(K1Cfg<CA>::NT, K1Cfg<CB>::NT));
+    if constexpr (std::is_same<CA, CB>::value) {
+        if (pa) hipLaunchKernelGGL((kb1_kernel<CA, CB, true, true, LP>), g, b1, 0, a.stream, a.reps, a.items, a.nitems, it, a.n_sweeps);
+        else hipLaunchKernelGGL((kb1_kernel<CA, CB, false, false, LP>), g, b1, 0, a.stream, a.reps, a.items, a.nitems, it, a.n_sweeps);
+    } else {
+        if (pa && pb)
+            hipLaunchKernelGGL((kb1_kernel<CA, CB, true, true, LP>), g, b1, 0, a.stream, a.reps, a.items, a.nitems, it, a.n_sweeps);
+        else if (pa)
+            hipLaunchKernelGGL((kb1_kernel<CA, CB, true, false, LP>), g, b1, 0, a.stream, a.reps, a.items, a.nitems, it, a.n_sweeps);
+        else if (pb)
+            hipLaunchKernelGGL((kb1_kernel<CA, CB, false, true, LP>), g, b1, 0, a.stream, a.reps, a.items, a.nitems, it, a.n_sweeps);
+        else
+            hipLaunchKernelGGL((kb1_kernel<CA, CB, false, false, LP>), g, b1, 0, a.stream, a.reps, a.items, a.nitems, it, a.n_sweeps);
+    }
+    if (a.k2w == 64)
+        hipLaunchKernelGGL((kb2_kernel<CA, CB, LP, 64>), g, dim3(64), 0, a.stream, a.reps, a.items, a.nitems, it, a.n_sweeps);
+    else
+        hipLaunchKernelGGL((kb2_kernel<CA, CB, LP, kBlock>), g, dim3(kBlock), 0, a.stream, a.reps, a.items, a.nitems, it, a.n_sweeps);
+    if (a.any_pcc && a.ncand > 0)
+        hipLaunchKernelGGL((kbc_kernel<CA, CB>), dim3(a.ncand), dim3(kBlock), 0, a.stream, a.reps, a.cand, a.ncand, it, a.n_sweeps);
+    hipLaunchKernelGGL((kb3a_kernel<CA, CB, LP>), g, dim3(64), 0, a.stream, a.reps, a.items, a.nitems, it, a.n_sweeps);
+    hipLaunchKernelGGL((kb3_kernel<CA, CB, LP>), g, dim3(kK3Block), 0, a.stream, a.reps, a.items, a.nitems, it, a.n_sweeps);
+}
+
+template <class CA, class CB>
+static void batch_sweeps(BatchArgs a, int merge_width, bool has3)
+{
+    // border-merge width: the asked one, else 256 threads when 3D tiles take
+    // part, else the 2D tile's default (one wave when its faces are small)
+    a.k2w = merge_width ? merge_width : (has3 ? kBlock : K2Cfg<CA>::NT);
+    const int rgrid = (a.nreps + kBlock - 1) / kBlock;
+    for (int it = 0; it < a.n_sweeps; ++it) {
+        if (a.loop) batch_phases<CA, CB, true>(a, it);
+        else batch_phases<CA, CB, false>(a, it);
+        if (a.any_pcc) {
+            if (a.nperc > 0)
+                hipLaunchKernelGGL(kbp_kernel, dim3(a.nperc), dim3(kBlock), 0, a.stream, a.reps, a.perc, a.nperc, it, a.n_sweeps);
+            hipLaunchKernelGGL(kbu_kernel, dim3(rgrid), dim3(kBlock), 0, a.stream, a.reps, a.nreps, it, a.n_sweeps);
+        }
+    }
+}
+
 int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, int nitems, const EngineItem* cand_items,
                  int ncand, const EngineItem* perc_items, int nperc, int n_sweeps, int any_pcc, int any_series,
-                 int any_3d, int grid, int item_grid, int merge_width, hipStream_t stream)
+                 int dims, int grid, int item_grid, int merge_width, hipStream_t stream)
 {
     const int rgrid = (nreps + kBlock - 1) / kBlock;
-    const bool pcc2 = (any_pcc & 1) != 0, pcc3 = (any_pcc & 2) != 0;   // a 2D / 3D PCC replica is active
-    const bool loop = item_grid < nitems;                                // workgroups take chunks of the list
-    const int ig = item_grid;
-    // border-merge width: the asked one, else one wave for a 2D-only batch whose
-    // tiles have small faces, else 256 threads
-    int k2w = merge_width;
-    if (!k2w) k2w = any_3d ? kBlock : 0;
+    const bool has2 = (dims & 1) != 0, has3 = (dims & 2) != 0;   // a 2D / 3D replica is active
+    BatchArgs a;
+    a.reps = reps;
+    a.items = items;
+    a.cand = cand_items;
+    a.perc = perc_items;
+    a.nreps = nreps;
+    a.nitems = nitems;
+    a.ncand = ncand;
+    a.nperc = nperc;
+    a.n_sweeps = n_sweeps;
+    a.any_pcc = any_pcc;
+    a.ig = item_grid;
+    a.k2w = 0;
+    a.loop = item_grid < nitems;   // workgroups take chunks of the list
+    a.stream = stream;
     switch (variant) {
-#define SW_PHASES(C2, C3, LP)                                                                                        \
-    {                                                                                                                \
-        const dim3 b1(max(K1Cfg<C2>::NT, K1Cfg<C3>::NT));                                                            \
-        if (pcc2 && pcc3)                                                                                            \
-            hipLaunchKernelGGL((kb1_kernel<C2, C3, true, true, LP>), dim3(ig), b1, 0, stream, reps, items, nitems, it, n_sweeps); \
-        else if (pcc2)                                                                                               \
-            hipLaunchKernelGGL((kb1_kernel<C2, C3, true, false, LP>), dim3(ig), b1, 0, stream, reps, items, nitems, it, n_sweeps); \
-        else if (pcc3)                                                                                               \
-            hipLaunchKernelGGL((kb1_kernel<C2, C3, false, true, LP>), dim3(ig), b1, 0, stream, reps, items, nitems, it, n_sweeps); \
-        else                                                                                                         \
-            hipLaunchKernelGGL((kb1_kernel<C2, C3, false, false, LP>), dim3(ig), b1, 0, stream, reps, items, nitems, it, n_sweeps); \
-        if (k2w == 64)                                                                                               \
-            hipLaunchKernelGGL((kb2_kernel<C2, C3, LP, 64>), dim3(ig), dim3(64), 0, stream, reps, items, nitems, it, n_sweeps); \
-        else                                                                                                         \
-            hipLaunchKernelGGL((kb2_kernel<C2, C3, LP, kBlock>), dim3(ig), dim3(kBlock), 0, stream, reps, items, nitems, it, n_sweeps); \
-        if (any_pcc && ncand > 0)                                                                                    \
-            hipLaunchKernelGGL((kbc_kernel<C2, C3>), dim3(ncand), dim3(kBlock), 0, stream, reps, cand_items, ncand, it, n_sweeps); \
-        hipLaunchKernelGGL((kb3a_kernel<C2, C3, LP>), dim3(ig), dim3(64), 0, stream, reps, items, nitems, it, n_sweeps); \
-        hipLaunchKernelGGL((kb3_kernel<C2, C3, LP>), dim3(ig), dim3(kK3Block), 0, stream, reps, items, nitems, it, n_sweeps); \
-    }
-#define SW_BATCH(i, C2, C3)                                                                                          \
-    case i:                                                                                                          \
-        if (!k2w) k2w = K2Cfg<C2>::NT;                                                                               \
-        for (int it = 0; it < n_sweeps; ++it) {                                                                      \
-            if (loop) SW_PHASES(C2, C3, true) else SW_PHASES(C2, C3, false)                                          \
-            if (any_pcc) {                                                                                           \
-                if (nperc > 0)                                                                                       \
-                    hipLaunchKernelGGL(kbp_kernel, dim3(nperc), dim3(kBlock), 0, stream, reps, perc_items, nperc, it, n_sweeps); \
-                hipLaunchKernelGGL(kbu_kernel, dim3(rgrid), dim3(kBlock), 0, stream, reps, nreps, it, n_sweeps);     \
-            }                                                                                                        \
-        }                                                                                                            \
+#define SW_BATCH(i, C2, C3)                                        \
+    case i:                                                        \
+        if (has2 && has3) batch_sweeps<C2, C3>(a, merge_width, true); \
+        else if (has3) batch_sweeps<C3, C3>(a, merge_width, true);   \
+        else batch_sweeps<C2, C2>(a, merge_width, false);            \
         break;
         SW_ENGINE_PAIRS(SW_BATCH)
+#undef SW_BATCH
         default: return -1;
     }
     if (any_series) hipLaunchKernelGGL(kbm_kernel, dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, n_sweeps);

@@ -662,7 +662,7 @@ int batched_sweep(sw_lattice* h, int32_t n)
         rep.dev_count_stale = false;
     }
     int pcc_dims = 0;   // bit 0: a 2D PCC replica is active, bit 1: a 3D one
-    bool any_series = false, any_3d = false;
+    bool any_series = false, any_3d = false, any_2d = false;
     for (size_t r = 0; r < h->reps.size(); ++r) {
         SwRep& m = h->reps[r].h;
         if (!m.active) continue;
@@ -671,6 +671,7 @@ int batched_sweep(sw_lattice* h, int32_t n)
         if (m.flags & FLAG_PCC) pcc_dims |= (m.dim == 2) ? 1 : 2;
         any_series = any_series || (m.flags & FLAG_SERIES);
         any_3d = any_3d || m.dim == 3;
+        any_2d = any_2d || m.dim == 2;
     }
     if (h->items_dirty || !h->items) {
         rc = build_items(h);
@@ -705,12 +706,13 @@ int batched_sweep(sw_lattice* h, int32_t n)
     const int grid = clamp_grid(device_cu_count() * (per_cu > 0 ? per_cu : 8));
     const int item_grid = per_cu > 0 ? clamp_grid(device_cu_count() * per_cu) : h->nitems;
     if (h->graph_n != n || h->graph_grid != grid || h->graph_item_grid != item_grid || h->graph_merge != h->merge_width ||
-        h->graph_flags != (int)(any_3d * 8 + pcc_dims * 2 + any_series) || h->graph_variant != variant) {
+        h->graph_flags != (int)(any_2d * 16 + any_3d * 8 + pcc_dims * 2 + any_series) || h->graph_variant != variant) {
         drop_graph(h);
         hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
         int lrc = launch_batch(variant, h->d_reps, (int)h->reps.size(), h->items, h->nitems, h->items + h->nitems,
-                               h->ncand, h->items + h->nitems + h->ncand, h->nperc, n, pcc_dims, any_series, any_3d,
+                               h->ncand, h->items + h->nitems + h->ncand, h->nperc, n, pcc_dims, any_series,
+                               (int)any_2d | ((int)any_3d << 1),
                                grid, item_grid, h->merge_width, h->stream);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(h->stream, &g);
@@ -728,7 +730,7 @@ int batched_sweep(sw_lattice* h, int32_t n)
         h->graph_grid = grid;
         h->graph_item_grid = item_grid;
         h->graph_merge = h->merge_width;
-        h->graph_flags = (int)(any_3d * 8 + pcc_dims * 2 + any_series);
+        h->graph_flags = (int)(any_2d * 16 + any_3d * 8 + pcc_dims * 2 + any_series);
         h->graph_variant = variant;
     }
     hipEvent_t ev;
