@@ -628,11 +628,13 @@ struct alignas(16) K1Smem {
     union {
         uint32_t ring[kBlock / 64][kRing];   // step 3: per-wave queue of pending unions
         struct {
-            int32_t pre[C::FBW];                   // border roots before each word of FB (their ranks)
-            alignas(16) uint16_t fst[2 * C::FT];   // tile-local labels of the near, then the far face sites
+            int32_t pre[C::FBW];             // border roots before each word of FB (their ranks)
+            union {
+                alignas(16) uint16_t fst[2 * C::FT];   // steps 4-4a: tile-local labels of the near, then the far face sites
+                K1Cov<C, PCC> cov;                     // step 4b (PCC)
+            };
         };
     };
-    K1Cov<C, PCC> cov;
 };
 
 // spins of 4 / 16 sites -> their up bits (a spin is up when it is positive)
@@ -789,9 +791,6 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
     for (int w = tid; w < C::FBW; w += blockDim.x) sm.FB[w] = 0;
     for (int k = 4 * tid; k < C::TS; k += 4 * (int)blockDim.x)
         *reinterpret_cast<uint4*>(&sm.par[k]) = make_uint4((uint32_t)k, (uint32_t)k + 1u, (uint32_t)k + 2u, (uint32_t)k + 3u);
-    if constexpr (PCC) {
-        for (int k = tid; k < K1Cov<C, true>::CAP; k += blockDim.x) sm.cov.a[k] = sm.cov.b[k] = 0ull;
-    }
     __syncthreads();
 
     // 2) bonds of the row's own links (x, d), each thread those of its part.
@@ -1108,6 +1107,9 @@ __device__ void k1_tile(const SwRep& R, int t, uint32_t s, uint64_t thr, K1Smem<
     // holds a PCC replica: only PCC replicas have coverage entries)
     if constexpr (PCC) if ((R.flags & (FLAG_PCC | FLAG_WIND)) == FLAG_PCC) {
         using CV = K1Cov<C, true>;
+        __syncthreads();   // the staged face labels are read: their space takes the coverage entries
+        for (int k = tid; k < CV::CAP; k += blockDim.x) sm.cov.a[k] = sm.cov.b[k] = 0ull;
+        __syncthreads();
         if (partok) {
             const unsigned long long rowb = (C::D == 3) ? ((1ull << ly) | (1ull << (C::TY + lz))) : (1ull << ly);
             uint32_t m = ss16;

@@ -340,14 +340,16 @@ __device__ __forceinline__ void item_range(int nitems, int& i0, int& i1)
 template <class C2, class C3, bool P2, bool P3>
 __device__ __forceinline__ void k1_item(const SwRep* reps, const EngineItem& item, int it, int n_sweeps, char* smem)
 {
-    const SwRep R = reps[item.rep];   // a private copy: stores to the lattice's arrays cannot alias it
+    const SwRep& R = reps[item.rep];
     uint32_t s;
     if (!rep_runs(R, it, n_sweeps, s)) return;
     int64_t* dst = nullptr;
     if ((R.flags & FLAG_SERIES) && s >= 1 && (it > 0 || R.measured < R.sweep))
         dst = R.series + 2 * (size_t)(s - 1 - R.first);
     int64_t e = 0, m = 0;
-    if (R.dim == 2)
+    if constexpr (std::is_same<C2, C3>::value && P2 == P3)   // a batch of one dimension: one copy of the tile code
+        k1_tile<C2, P2>(R, item.tile, s, R.thr, *reinterpret_cast<K1Smem<C2, P2>*>(smem), dst != nullptr, e, m);
+    else if (R.dim == 2)
         k1_tile<C2, P2>(R, item.tile, s, R.thr, *reinterpret_cast<K1Smem<C2, P2>*>(smem), dst != nullptr, e, m);
     else
         k1_tile<C3, P3>(R, item.tile, s, R.thr, *reinterpret_cast<K1Smem<C3, P3>*>(smem), dst != nullptr, e, m);
@@ -360,7 +362,8 @@ __device__ __forceinline__ void k2_item(const SwRep* reps, const EngineItem& ite
     const SwRep R = reps[item.rep];   // a private copy: stores to the lattice's arrays cannot alias it
     uint32_t s;
     if (!rep_runs(R, it, n_sweeps, s)) return;
-    if (R.dim == 2) k2_tile<C2, NT>(R, item.tile, *reinterpret_cast<K2Smem<C2>*>(smem));
+    if constexpr (std::is_same<C2, C3>::value) k2_tile<C2, NT>(R, item.tile, *reinterpret_cast<K2Smem<C2>*>(smem));
+    else if (R.dim == 2) k2_tile<C2, NT>(R, item.tile, *reinterpret_cast<K2Smem<C2>*>(smem));
     else k2_tile<C3, NT>(R, item.tile, *reinterpret_cast<K2Smem<C3>*>(smem));
 }
 
@@ -371,7 +374,8 @@ __device__ __forceinline__ void kc_item(const SwRep* reps, const EngineItem& ite
     const SwRep R = reps[item.rep];
     uint32_t s;
     if ((R.flags & (FLAG_PCC | FLAG_WIND)) != FLAG_PCC || !rep_runs(R, it, n_sweeps, s)) return;
-    if (R.dim == 2) k_cand_tile<C2>(R, item.tile, s);
+    if constexpr (std::is_same<C2, C3>::value) k_cand_tile<C2>(R, item.tile, s);
+    else if (R.dim == 2) k_cand_tile<C2>(R, item.tile, s);
     else k_cand_tile<C3>(R, item.tile, s);
 }
 
@@ -384,7 +388,8 @@ __device__ __forceinline__ void k3a_item(const SwRep* reps, const EngineItem& it
     if (!rep_runs(R, it, n_sweeps, s)) return;
     wave_lds_sync();   // the previous item's reads of the tables are done
     CovArgs cov;
-    if (R.dim == 2) k3a_tile<C2>(R, item.tile, s, *reinterpret_cast<K3aSmem<C2>*>(smem), cov);
+    if constexpr (std::is_same<C2, C3>::value) k3a_tile<C2>(R, item.tile, s, *reinterpret_cast<K3aSmem<C2>*>(smem), cov);
+    else if (R.dim == 2) k3a_tile<C2>(R, item.tile, s, *reinterpret_cast<K3aSmem<C2>*>(smem), cov);
     else k3a_tile<C3>(R, item.tile, s, *reinterpret_cast<K3aSmem<C3>*>(smem), cov);
     if (cov.nl >= 0) k3a_coverage(cov);
 }
@@ -395,7 +400,8 @@ __device__ __forceinline__ void k3_item(const SwRep* reps, const EngineItem& ite
     const SwRep& R = reps[item.rep];
     uint32_t s;
     if (!rep_runs(R, it, n_sweeps, s)) return;
-    if (R.dim == 2) k3_tile<C2>(R, item.tile, s, *reinterpret_cast<K3Smem<C2>*>(smem));
+    if constexpr (std::is_same<C2, C3>::value) k3_tile<C2>(R, item.tile, s, *reinterpret_cast<K3Smem<C2>*>(smem));
+    else if (R.dim == 2) k3_tile<C2>(R, item.tile, s, *reinterpret_cast<K3Smem<C2>*>(smem));
     else k3_tile<C3>(R, item.tile, s, *reinterpret_cast<K3Smem<C3>*>(smem));
 }
 
