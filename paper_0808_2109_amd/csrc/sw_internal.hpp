@@ -38,7 +38,7 @@ int launch_set_state(SwRep* d, uint32_t sweep, uint32_t measured, uint32_t first
 // (replica, k) for the candidate slots [k * kPercChunk, (k + 1) * kPercChunk)
 int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, int nitems, const EngineItem* cand_items,
                  int ncand, const EngineItem* perc_items, int nperc, int n_sweeps, int any_pcc, int any_series,
-                 int dims, int grid, int item_grid, int merge_width, hipStream_t stream);
+                 int dims, int nitems2, int ncand2, int grid, int item_grid, int merge_width, hipStream_t stream);
 // all n sweeps of a batch in persistent launches (one per 4096 sweeps) of
 // co-resident workgroups, per_cu of them per CU (0: as many as fit); bar: a
 // device word the launches use as their barrier; grid_used: the grid

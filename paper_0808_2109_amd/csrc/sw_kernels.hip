@@ -889,30 +889,54 @@ static void batch_phases(const BatchArgs& a, int it)
     hipLaunchKernelGGL((kb3_kernel<CA, CB, LP>), g, dim3(kK3Block), 0, a.stream, a.reps, a.items, a.nitems, it, a.n_sweeps);
 }
 
-template <class CA, class CB>
-static void batch_sweeps(BatchArgs a, int merge_width, bool has3)
+// the sweeps of a batch: a batch of one dimension runs its phases with that
+// dimension's kernels; a mixed one runs, phase group by phase group, the 2D
+// items (the front of the work lists) and then the 3D items with kernels of
+// their own dimension, so that no workgroup or register budget is sized for
+// the other dimension's tile
+template <class C2, class C3>
+static void batch_sweeps(const BatchArgs& all, int merge_width, bool has2, bool has3, int nitems2, int ncand2,
+                         int item_grid)
 {
-    // border-merge width: the asked one, else 256 threads when 3D tiles take
-    // part, else the 2D tile's default (one wave when its faces are small)
-    a.k2w = merge_width ? merge_width : (has3 ? kBlock : K2Cfg<CA>::NT);
-    const int rgrid = (a.nreps + kBlock - 1) / kBlock;
-    for (int it = 0; it < a.n_sweeps; ++it) {
-        if (a.loop) batch_phases<CA, CB, true>(a, it);
-        else batch_phases<CA, CB, false>(a, it);
-        if (a.any_pcc) {
-            if (a.nperc > 0)
-                hipLaunchKernelGGL(kbp_kernel, dim3(a.nperc), dim3(kBlock), 0, a.stream, a.reps, a.perc, a.nperc, it, a.n_sweeps);
-            hipLaunchKernelGGL(kbu_kernel, dim3(rgrid), dim3(kBlock), 0, a.stream, a.reps, a.nreps, it, a.n_sweeps);
+    auto part = [&](int i0, int n, int c0, int nc, int k2w_default) {
+        BatchArgs a = all;
+        a.items = all.items + i0;
+        a.nitems = n;
+        a.cand = all.cand + c0;
+        a.ncand = nc;
+        a.loop = item_grid < n;           // workgroups take chunks of the list
+        a.ig = a.loop ? item_grid : n;
+        a.k2w = merge_width ? merge_width : k2w_default;
+        return a;
+    };
+    const BatchArgs a2 = part(0, nitems2, 0, ncand2, K2Cfg<C2>::NT);
+    const BatchArgs a3 = part(nitems2, all.nitems - nitems2, ncand2, all.ncand - ncand2, kBlock);
+    const int rgrid = (all.nreps + kBlock - 1) / kBlock;
+    for (int it = 0; it < all.n_sweeps; ++it) {
+        if (has2) {
+            if (a2.loop) batch_phases<C2, C2, true>(a2, it);
+            else batch_phases<C2, C2, false>(a2, it);
+        }
+        if (has3) {
+            if (a3.loop) batch_phases<C3, C3, true>(a3, it);
+            else batch_phases<C3, C3, false>(a3, it);
+        }
+        if (all.any_pcc) {
+            if (all.nperc > 0)
+                hipLaunchKernelGGL(kbp_kernel, dim3(all.nperc), dim3(kBlock), 0, all.stream, all.reps, all.perc, all.nperc,
+                                   it, all.n_sweeps);
+            hipLaunchKernelGGL(kbu_kernel, dim3(rgrid), dim3(kBlock), 0, all.stream, all.reps, all.nreps, it, all.n_sweeps);
         }
     }
 }
 
 int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, int nitems, const EngineItem* cand_items,
                  int ncand, const EngineItem* perc_items, int nperc, int n_sweeps, int any_pcc, int any_series,
-                 int dims, int grid, int item_grid, int merge_width, hipStream_t stream)
+                 int dims, int nitems2, int ncand2, int grid, int item_grid, int merge_width, hipStream_t stream)
 {
     const int rgrid = (nreps + kBlock - 1) / kBlock;
     const bool has2 = (dims & 1) != 0, has3 = (dims & 2) != 0;   // a 2D / 3D replica is active
+    if (nitems2 < 0 || nitems2 > nitems || ncand2 < 0 || ncand2 > ncand) return -1;
     BatchArgs a;
     a.reps = reps;
     a.items = items;
@@ -926,14 +950,12 @@ int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, i
     a.any_pcc = any_pcc;
     a.ig = item_grid;
     a.k2w = 0;
-    a.loop = item_grid < nitems;   // workgroups take chunks of the list
+    a.loop = false;
     a.stream = stream;
     switch (variant) {
-#define SW_BATCH(i, C2, C3)                                        \
-    case i:                                                        \
-        if (has2 && has3) batch_sweeps<C2, C3>(a, merge_width, true); \
-        else if (has3) batch_sweeps<C3, C3>(a, merge_width, true);   \
-        else batch_sweeps<C2, C2>(a, merge_width, false);            \
+#define SW_BATCH(i, C2, C3)                                                                       \
+    case i:                                                                                       \
+        batch_sweeps<C2, C3>(a, merge_width, has2, has3, nitems2, ncand2, item_grid);            \
         break;
         SW_ENGINE_PAIRS(SW_BATCH)
 #undef SW_BATCH

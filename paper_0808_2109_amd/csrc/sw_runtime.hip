@@ -585,12 +585,16 @@ int plain_sweep(sw_lattice* h, int r, int32_t n)
     return SW_OK;
 }
 
+// The work lists hold the 2D replicas' items first, then the 3D ones, so that
+// a mixed batch runs as two passes of single-dimension kernels.
 static int build_items(sw_lattice* h)
 {
     std::vector<EngineItem> items, cand, perc;
+    int n2 = 0, c2 = 0;
+    for (int dim = 2; dim <= 3; ++dim)
     for (size_t r = 0; r < h->reps.size(); ++r) {
         const SwRep& m = h->reps[r].h;
-        if (!m.active) continue;
+        if (!m.active || m.dim != dim) continue;
         for (int t = 0; t < m.ntiles; ++t) {
             items.push_back(EngineItem{(int32_t)r, t});
             const int ix = t % m.ntx, iy = (t / m.ntx) % m.nty, iz = t / (m.ntx * m.nty);
@@ -602,7 +606,11 @@ static int build_items(sw_lattice* h)
             for (int64_t k = 0; k * kPercChunk < nslots; ++k) perc.push_back(EngineItem{(int32_t)r, (int32_t)k});
         }
     }
+    for (const EngineItem& it : items) n2 += h->reps[it.rep].h.dim == 2;
+    for (const EngineItem& it : cand) c2 += h->reps[it.rep].h.dim == 2;
     const size_t nlist = items.size();
+    h->nitems2 = n2;
+    h->ncand2 = c2;
     h->ncand = (int)cand.size();
     h->nperc = (int)perc.size();
     items.insert(items.end(), cand.begin(), cand.end());
@@ -712,7 +720,7 @@ int batched_sweep(sw_lattice* h, int32_t n)
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
         int lrc = launch_batch(variant, h->d_reps, (int)h->reps.size(), h->items, h->nitems, h->items + h->nitems,
                                h->ncand, h->items + h->nitems + h->ncand, h->nperc, n, pcc_dims, any_series,
-                               (int)any_2d | ((int)any_3d << 1),
+                               (int)any_2d | ((int)any_3d << 1), h->nitems2, h->ncand2,
                                grid, item_grid, h->merge_width, h->stream);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(h->stream, &g);

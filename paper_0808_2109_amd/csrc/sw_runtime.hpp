@@ -66,6 +66,8 @@ struct sw_lattice {
     int nitems = 0;
     int ncand = 0;                       // PCC tiles on a hyperplane x_a = 0 (after the work list)
     int nperc = 0;                       // PCC slot chunks (after the candidate list)
+    int nitems2 = 0;                     // 2D items at the front of the work list (3D ones follow)
+    int ncand2 = 0;                      // 2D items at the front of the candidate list
     bool items_dirty = true;
     int batch_per_cu = 0;               // workgroups per CU of the batched phase launches (0: one per tile)
     int merge_width = 0;                // threads per tile of the border merge (0: the tile's default, 64, 256)
