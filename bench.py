@@ -513,12 +513,12 @@ def run_plain(swgpu, workloads, steps: int, warmup: int, autotune: bool):
     import torch
 
     wl = workloads.plain()
-    # one stream for both lattices: their sweeps run one after the other, so
-    # every kernel's event-timed duration is its own, not shared with the other
-    # lattice's kernels
-    stream = torch.cuda.Stream()
-    handle = ctypes.c_void_p(stream.cuda_stream)
-    lats = [swgpu.Lattice(swgpu.params_from_replica(rep), stream=handle) for rep in wl.replicas]
+    # one stream per lattice: the two lattices are independent, so their sweeps
+    # may overlap on the device (a latency-bound merge of one lattice beside
+    # the labelling of the other)
+    streams = [torch.cuda.Stream() for _ in wl.replicas]
+    lats = [swgpu.Lattice(swgpu.params_from_replica(rep), stream=ctypes.c_void_p(st.cuda_stream))
+            for rep, st in zip(wl.replicas, streams)]
     log(f"workload {wl.name}: {[r.nsites for r in wl.replicas]} sites, warmup {warmup}, steps {steps}")
     # warm up first: the autotuner times the tile shapes on a copy of the
     # current (equilibrated) state
@@ -531,7 +531,7 @@ def run_plain(swgpu, workloads, steps: int, warmup: int, autotune: bool):
             lat.autotune(sweeps=3)
     shapes = [swgpu.tile_shapes(r.dim)[lat.tile_shape(0)] for r, lat in zip(wl.replicas, lats)]
     torch.cuda.synchronize()
-    # the timed steps: nothing but the sweeps on the stream
+    # the timed steps: nothing but the sweeps, each lattice on its own stream
     t0 = time.perf_counter()
     for _ in range(steps):
         for lat in lats:
@@ -539,15 +539,17 @@ def run_plain(swgpu, workloads, steps: int, warmup: int, autotune: bool):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     # the same number of steps again with a HIP event pair around every
-    # launch, for the per-kernel durations (the events add their own packets
-    # to the stream, so this pass is not the one `value` comes from)
+    # launch, for the per-kernel durations; here each lattice's sweep waits
+    # for the other's to end, so that every event-timed duration is the
+    # kernel's own (neither the events nor the waits are in `value`'s pass)
     for lat in lats:
         lat.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        for lat in lats:
+        for lat, st in zip(lats, streams):
             lat.sweep(1)
+            st.synchronize()
     torch.cuda.synchronize()
     dt_events = time.perf_counter() - t0
     timings = [lat.timing() for lat in lats]

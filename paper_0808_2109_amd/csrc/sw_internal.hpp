@@ -44,8 +44,8 @@ int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, i
 // device word the launches use as their barrier; grid_used: the grid
 int launch_persistent(int variant, SwRep* reps, int nreps, const EngineItem* items, int nitems,
                       const EngineItem* cand_items, int ncand, const EngineItem* perc_items, int nperc, int n_sweeps,
-                      int any_pcc, int any_series, int per_cu, uint32_t* bar, int32_t* err, hipStream_t stream,
-                      int* grid_used);
+                      int any_pcc, int any_series, int dims, int per_cu, uint32_t* bar, int32_t* err,
+                      hipStream_t stream, int* grid_used);
 
 int shape_count(int dim);
 int shape_extents(int dim, int id, int* tx, int* ty, int* tz);

@@ -966,13 +966,22 @@ int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, i
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
+// the persistent kernel for the tile pair (C2, C3); a batch of one dimension
+// passes that dimension's tile for both, so that the kernel carries one copy
+// of the tile code and is sized for that tile alone
 template <class C2, class C3>
 static const void* persist_fn(bool pcc2, bool pcc3)
 {
-    if (pcc2 && pcc3) return reinterpret_cast<const void*>(&kpersist_kernel<C2, C3, true, true>);
-    if (pcc2) return reinterpret_cast<const void*>(&kpersist_kernel<C2, C3, true, false>);
-    if (pcc3) return reinterpret_cast<const void*>(&kpersist_kernel<C2, C3, false, true>);
-    return reinterpret_cast<const void*>(&kpersist_kernel<C2, C3, false, false>);
+    if constexpr (std::is_same<C2, C3>::value) {
+        const bool p = (C2::D == 2) ? pcc2 : pcc3;
+        return p ? reinterpret_cast<const void*>(&kpersist_kernel<C2, C3, true, true>)
+                 : reinterpret_cast<const void*>(&kpersist_kernel<C2, C3, false, false>);
+    } else {
+        if (pcc2 && pcc3) return reinterpret_cast<const void*>(&kpersist_kernel<C2, C3, true, true>);
+        if (pcc2) return reinterpret_cast<const void*>(&kpersist_kernel<C2, C3, true, false>);
+        if (pcc3) return reinterpret_cast<const void*>(&kpersist_kernel<C2, C3, false, true>);
+        return reinterpret_cast<const void*>(&kpersist_kernel<C2, C3, false, false>);
+    }
 }
 
 // Sweeps per persistent launch: at most 4096, and few enough that the
@@ -987,14 +996,18 @@ static int persist_chunk(int nitems, int grid)
 
 int launch_persistent(int variant, SwRep* reps, int nreps, const EngineItem* items, int nitems,
                       const EngineItem* cand_items, int ncand, const EngineItem* perc_items, int nperc, int n_sweeps,
-                      int any_pcc, int any_series, int per_cu, uint32_t* bar, int32_t* err, hipStream_t stream,
-                      int* grid_used)
+                      int any_pcc, int any_series, int dims, int per_cu, uint32_t* bar, int32_t* err,
+                      hipStream_t stream, int* grid_used)
 {
     const bool pcc2 = (any_pcc & 1) != 0, pcc3 = (any_pcc & 2) != 0;
+    const bool has2 = (dims & 1) != 0, has3 = (dims & 2) != 0;
     const void* fn = nullptr;
     switch (variant) {
-#define SW_PERSIST(i, C2, C3) \
-    case i: fn = persist_fn<C2, C3>(pcc2, pcc3); break;
+#define SW_PERSIST(i, C2, C3)                                                                          \
+    case i:                                                                                            \
+        fn = (has2 && has3) ? persist_fn<C2, C3>(pcc2, pcc3)                                           \
+                            : has3 ? persist_fn<C3, C3>(pcc2, pcc3) : persist_fn<C2, C2>(pcc2, pcc3); \
+        break;
         SW_ENGINE_PAIRS(SW_PERSIST)
 #undef SW_PERSIST
         default: return -1;

@@ -703,7 +703,8 @@ int batched_sweep(sw_lattice* h, int32_t n)
         timing_begin(h, 5, &ev);
         int lrc = launch_persistent(variant, h->d_reps, (int)h->reps.size(), h->items, h->nitems, h->items + h->nitems,
                                     h->ncand, h->items + h->nitems + h->ncand, h->nperc, n, pcc_dims, any_series,
-                                    per_cu, h->bar, h->err, h->stream, &h->persist_grid);
+                                    (int)any_2d | ((int)any_3d << 1), per_cu, h->bar, h->err, h->stream,
+                                    &h->persist_grid);
         timing_end(h, 5, ev);
         if (lrc) return fail(SW_EHIP, "persistent batched launch failed (%d)", lrc);
         h->mirror_stale = true;
