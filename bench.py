@@ -188,7 +188,8 @@ def _db_rows(db_dir: str, query: str):
         con.close()
 
 
-def summarize_profiles(prof_dir: str, out_dir: str, trace_cmd: str, pmc_cmd: str, copy_cmd: str):
+def summarize_profiles(prof_dir: str, out_dir: str, trace_cmd: str, pmc_cmd: str, copy_cmd: str,
+                       event_steps: int = 200):
     """Kernel-trace statistics and HBM traffic per launch from rocprofv3 runs.
 
     prof_dir holds the databases of five runs: trace/ (--kernel-trace --stats),
@@ -199,23 +200,30 @@ def summarize_profiles(prof_dir: str, out_dir: str, trace_cmd: str, pmc_cmd: str
     import collections
 
     os.makedirs(out_dir, exist_ok=True)
-    # 1) kernel trace: calls, mean / min / max duration per kernel
-    rows = _db_rows(os.path.join(prof_dir, "trace"), "select name, duration from kernels")
+    # 1) kernel trace: calls, mean / min / max duration per kernel, and the
+    #    mean over the last `event_steps` launches of each plain-path kernel:
+    #    the pass in which the bench times every launch with events, with the
+    #    lattices' sweeps one after the other (in the pass before it the two
+    #    lattices' kernels may overlap)
+    rows = _db_rows(os.path.join(prof_dir, "trace"), "select name, duration from kernels order by start")
     stats = collections.defaultdict(list)
     for name, dur in rows:
         stats[name].append(dur / 1e3)
     total = sum(sum(v) for v in stats.values())
     lines = [f"# rocprofv3 kernel trace, plain sweep workload (8192^2 at T_c + 256^3 at T=4.5115)",
-             f"# command: {trace_cmd}", "#",
-             f"# {'calls':>6} {'mean_us':>10} {'min_us':>10} {'max_us':>10} {'share':>7}  kernel"]
-    for name, v in sorted(stats.items(), key=lambda kv: -sum(kv[1])):
-        lines.append(f"  {len(v):6d} {sum(v) / len(v):10.2f} {min(v):10.2f} {max(v):10.2f} "
-                     f"{100 * sum(v) / total:6.1f}%  {name[:110]}")
+             f"# command: {trace_cmd}",
+             f"# event_pass_us: mean over the last {event_steps} launches (the bench's event-timed pass, each kernel alone)",
+             "#",
+             f"# {'calls':>6} {'mean_us':>10} {'event_pass_us':>14} {'min_us':>10} {'max_us':>10} {'share':>7}  kernel"]
     trace_means = {}
-    for name, v in stats.items():
+    for name, v in sorted(stats.items(), key=lambda kv: -sum(kv[1])):
         k = _kernel_of(name)
-        if k:
-            trace_means[f"{k[0]}:{k[1]}"] = sum(v) / len(v)
+        tail = v[-event_steps:] if k and len(v) >= event_steps else None
+        ev = f"{sum(tail) / len(tail):14.2f}" if tail else f"{'-':>14}"
+        lines.append(f"  {len(v):6d} {sum(v) / len(v):10.2f} {ev} {min(v):10.2f} {max(v):10.2f} "
+                     f"{100 * sum(v) / total:6.1f}%  {name[:110]}")
+        if tail:
+            trace_means[f"{k[0]}:{k[1]}"] = sum(tail) / len(tail)
     with open(os.path.join(out_dir, PROFILE_PREFIX + "_kernel_trace.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
 
