@@ -89,9 +89,13 @@ MIX = [
 ]
 
 
-def test_open_and_periodic_batched_together():
+@pytest.mark.parametrize("engine", [swgpu.SW_ENGINE_GRAPH, swgpu.SW_ENGINE_PERSISTENT])
+def test_open_and_periodic_batched_together(engine):
+    """Open and periodic boxes, int8 and bit-packed, PCC among them, in one
+    batch: through the phase-kernel graph and through the persistent kernel."""
     with swgpu.Lattice([_params(s) for s in MIX]) as lat:
         lat.set_mode(swgpu.SW_MODE_BATCHED)
+        lat.set_batch_engine(engine)
         lat.sweep(3)
         lat.sweep(3)
         for r, spec in enumerate(MIX):

@@ -72,11 +72,13 @@ MIX = [
 ]
 
 
-@pytest.mark.parametrize("per_cu", [0, 1])
-def test_winding_in_a_batch(per_cu):
+@pytest.mark.parametrize("per_cu,engine", [(0, swgpu.SW_ENGINE_GRAPH), (1, swgpu.SW_ENGINE_GRAPH),
+                                           (0, swgpu.SW_ENGINE_PERSISTENT)])
+def test_winding_in_a_batch(per_cu, engine):
     with swgpu.Lattice([_params(s) for s in MIX]) as lat:
         lat.set_mode(swgpu.SW_MODE_BATCHED)
         lat.set_batch_grid(per_cu)
+        lat.set_batch_engine(engine)
         lat.sweep(5)
         lat.sweep(7)
         for r, spec in enumerate(MIX):
