@@ -36,9 +36,21 @@ int launch_set_state(SwRep* d, uint32_t sweep, uint32_t measured, uint32_t first
 // per-tile phase kernels, nitems for one workgroup per work item)
 // cand_items: the tiles of PCC replicas on a hyperplane x_a = 0; perc_items:
 // (replica, k) for the candidate slots [k * kPercChunk, (k + 1) * kPercChunk)
+// A batch runs as one or two groups of replicas, each of one dimension; each
+// group's work items, candidate tiles, slot chunks and replicas are a
+// contiguous range of its list.  Two groups run on two streams (forked from
+// and joined back to the first), so that their phases may overlap.
+struct BatchGroup {
+    int item0, nitems;     // work list
+    int cand0, ncand;      // PCC candidate list
+    int perc0, nperc;      // PCC slot list
+    int rep0, nrep;        // replica list
+    int dim;
+};
 int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, int nitems, const EngineItem* cand_items,
-                 int ncand, const EngineItem* perc_items, int nperc, int n_sweeps, int any_pcc, int any_series,
-                 int dims, int nitems2, int ncand2, int grid, int item_grid, int merge_width, hipStream_t stream);
+                 const EngineItem* perc_items, const EngineItem* rep_list, const BatchGroup* groups, int ngroups,
+                 int n_sweeps, int any_pcc, int any_series, int grid, int item_grid, int merge_width,
+                 hipStream_t stream, hipStream_t side, hipEvent_t fork, hipEvent_t join);
 // all n sweeps of a batch in persistent launches (one per 4096 sweeps) of
 // co-resident workgroups, per_cu of them per CU (0: as many as fit); bar: a
 // device word the launches use as their barrier; grid_used: the grid

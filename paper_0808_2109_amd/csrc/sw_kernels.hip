@@ -500,6 +500,14 @@ __global__ __launch_bounds__(kBlock) void kbu_kernel(SwRep* reps, int nreps, int
     if (r < nreps) update_rep(reps, r, it, n_sweeps);
 }
 
+// PCC feedback of the replicas of one group of a batch (their indices in list)
+__global__ __launch_bounds__(kBlock) void kbu_list_kernel(SwRep* reps, const EngineItem* list, int n, int it,
+                                                          int n_sweeps)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) update_rep(reps, list[i].rep, it, n_sweeps);
+}
+
 // E, M after the last sweep of every recording replica
 __global__ __launch_bounds__(kBlock) void kbm_kernel(SwRep* reps, const EngineItem* items, int nitems, int n_sweeps)
 {
@@ -889,77 +897,70 @@ static void batch_phases(const BatchArgs& a, int it)
     hipLaunchKernelGGL((kb3_kernel<CA, CB, LP>), g, dim3(kK3Block), 0, a.stream, a.reps, a.items, a.nitems, it, a.n_sweeps);
 }
 
-// the sweeps of a batch: a batch of one dimension runs its phases with that
-// dimension's kernels; a mixed one runs, phase group by phase group, the 2D
-// items (the front of the work lists) and then the 3D items with kernels of
-// their own dimension, so that no workgroup or register budget is sized for
-// the other dimension's tile
-template <class C2, class C3>
-static void batch_sweeps(const BatchArgs& all, int merge_width, bool has2, bool has3, int nitems2, int ncand2,
-                         int item_grid)
+// the sweeps of one group of a batch (one dimension, tile C) on `stream`: each
+// sweep's phases over the group's work list, then its PCC test and feedback
+template <class C>
+static void group_sweeps(BatchArgs a, const EngineItem* perc, int nperc, const EngineItem* reps_of, int nrep,
+                         int merge_width, int item_grid)
 {
-    auto part = [&](int i0, int n, int c0, int nc, int k2w_default) {
-        BatchArgs a = all;
-        a.items = all.items + i0;
-        a.nitems = n;
-        a.cand = all.cand + c0;
-        a.ncand = nc;
-        a.loop = item_grid < n;           // workgroups take chunks of the list
-        a.ig = a.loop ? item_grid : n;
-        a.k2w = merge_width ? merge_width : k2w_default;
-        return a;
-    };
-    const BatchArgs a2 = part(0, nitems2, 0, ncand2, K2Cfg<C2>::NT);
-    const BatchArgs a3 = part(nitems2, all.nitems - nitems2, ncand2, all.ncand - ncand2, kBlock);
-    const int rgrid = (all.nreps + kBlock - 1) / kBlock;
-    for (int it = 0; it < all.n_sweeps; ++it) {
-        if (has2) {
-            if (a2.loop) batch_phases<C2, C2, true>(a2, it);
-            else batch_phases<C2, C2, false>(a2, it);
-        }
-        if (has3) {
-            if (a3.loop) batch_phases<C3, C3, true>(a3, it);
-            else batch_phases<C3, C3, false>(a3, it);
-        }
-        if (all.any_pcc) {
-            if (all.nperc > 0)
-                hipLaunchKernelGGL(kbp_kernel, dim3(all.nperc), dim3(kBlock), 0, all.stream, all.reps, all.perc, all.nperc,
-                                   it, all.n_sweeps);
-            hipLaunchKernelGGL(kbu_kernel, dim3(rgrid), dim3(kBlock), 0, all.stream, all.reps, all.nreps, it, all.n_sweeps);
+    a.loop = item_grid < a.nitems;   // workgroups take chunks of the list
+    a.ig = a.loop ? item_grid : a.nitems;
+    a.k2w = merge_width ? merge_width : (C::D == 3 ? kBlock : K2Cfg<C>::NT);
+    for (int it = 0; it < a.n_sweeps; ++it) {
+        if (a.loop) batch_phases<C, C, true>(a, it);
+        else batch_phases<C, C, false>(a, it);
+        if (a.any_pcc) {
+            if (nperc > 0)
+                hipLaunchKernelGGL(kbp_kernel, dim3(nperc), dim3(kBlock), 0, a.stream, a.reps, perc, nperc, it, a.n_sweeps);
+            hipLaunchKernelGGL(kbu_list_kernel, dim3((nrep + kBlock - 1) / kBlock), dim3(kBlock), 0, a.stream, a.reps,
+                               reps_of, nrep, it, a.n_sweeps);
         }
     }
 }
 
 int launch_batch(int variant, SwRep* reps, int nreps, const EngineItem* items, int nitems, const EngineItem* cand_items,
-                 int ncand, const EngineItem* perc_items, int nperc, int n_sweeps, int any_pcc, int any_series,
-                 int dims, int nitems2, int ncand2, int grid, int item_grid, int merge_width, hipStream_t stream)
+                 const EngineItem* perc_items, const EngineItem* rep_list, const BatchGroup* groups, int ngroups,
+                 int n_sweeps, int any_pcc, int any_series, int grid, int item_grid, int merge_width,
+                 hipStream_t stream, hipStream_t side, hipEvent_t fork, hipEvent_t join)
 {
+    if (ngroups < 1 || ngroups > 2 || (ngroups == 2 && (!side || !fork || !join))) return -1;
     const int rgrid = (nreps + kBlock - 1) / kBlock;
-    const bool has2 = (dims & 1) != 0, has3 = (dims & 2) != 0;   // a 2D / 3D replica is active
-    if (nitems2 < 0 || nitems2 > nitems || ncand2 < 0 || ncand2 > ncand) return -1;
-    BatchArgs a;
-    a.reps = reps;
-    a.items = items;
-    a.cand = cand_items;
-    a.perc = perc_items;
-    a.nreps = nreps;
-    a.nitems = nitems;
-    a.ncand = ncand;
-    a.nperc = nperc;
-    a.n_sweeps = n_sweeps;
-    a.any_pcc = any_pcc;
-    a.ig = item_grid;
-    a.k2w = 0;
-    a.loop = false;
-    a.stream = stream;
-    switch (variant) {
-#define SW_BATCH(i, C2, C3)                                                                       \
-    case i:                                                                                       \
-        batch_sweeps<C2, C3>(a, merge_width, has2, has3, nitems2, ncand2, item_grid);            \
+    if (ngroups == 2) {   // the second group's stream starts after everything before the call
+        if (hipEventRecord(fork, stream) != hipSuccess || hipStreamWaitEvent(side, fork, 0) != hipSuccess) return -3;
+    }
+    for (int g = 0; g < ngroups; ++g) {
+        const BatchGroup& G = groups[g];
+        if (G.nitems <= 0) continue;
+        BatchArgs a;
+        a.reps = reps;
+        a.items = items + G.item0;
+        a.nitems = G.nitems;
+        a.cand = cand_items + G.cand0;
+        a.ncand = G.ncand;
+        a.perc = perc_items + G.perc0;
+        a.nperc = G.nperc;
+        a.nreps = nreps;
+        a.n_sweeps = n_sweeps;
+        a.any_pcc = any_pcc;
+        a.ig = 0;
+        a.k2w = 0;
+        a.loop = false;
+        a.stream = (g == 0) ? stream : side;
+        const EngineItem* perc = perc_items + G.perc0;
+        const EngineItem* rl = rep_list + G.rep0;
+        switch (variant) {
+#define SW_GROUP(i, C2, C3)                                                                     \
+    case i:                                                                                     \
+        if (G.dim == 3) group_sweeps<C3>(a, perc, G.nperc, rl, G.nrep, merge_width, item_grid); \
+        else group_sweeps<C2>(a, perc, G.nperc, rl, G.nrep, merge_width, item_grid);            \
         break;
-        SW_ENGINE_PAIRS(SW_BATCH)
-#undef SW_BATCH
-        default: return -1;
+            SW_ENGINE_PAIRS(SW_GROUP)
+#undef SW_GROUP
+            default: return -1;
+        }
+    }
+    if (ngroups == 2) {   // and the first waits for the second
+        if (hipEventRecord(join, side) != hipSuccess || hipStreamWaitEvent(stream, join, 0) != hipSuccess) return -3;
     }
     if (any_series) hipLaunchKernelGGL(kbm_kernel, dim3(grid), dim3(kBlock), 0, stream, reps, items, nitems, n_sweeps);
     hipLaunchKernelGGL(kbfin_kernel, dim3(rgrid), dim3(kBlock), 0, stream, reps, nreps, n_sweeps);

@@ -585,36 +585,79 @@ int plain_sweep(sw_lattice* h, int r, int32_t n)
     return SW_OK;
 }
 
-// The work lists hold the 2D replicas' items first, then the 3D ones, so that
-// a mixed batch runs as two passes of single-dimension kernels.
+// The batch's groups: a mixed batch has its 2D replicas in one group and its
+// 3D ones in the other; a batch of one dimension with enough tiles to fill
+// the device twice over is split into two halves of about equal sites (the
+// largest replica first, each to the lighter half); a small one is one group.
+// The work lists hold group 0's entries, then group 1's.
 static int build_items(sw_lattice* h)
 {
-    std::vector<EngineItem> items, cand, perc;
-    int n2 = 0, c2 = 0;
-    for (int dim = 2; dim <= 3; ++dim)
+    std::vector<int> grp(h->reps.size(), -1);
+    bool has2 = false, has3 = false;
+    int64_t tiles = 0;
     for (size_t r = 0; r < h->reps.size(); ++r) {
         const SwRep& m = h->reps[r].h;
-        if (!m.active || m.dim != dim) continue;
-        for (int t = 0; t < m.ntiles; ++t) {
-            items.push_back(EngineItem{(int32_t)r, t});
-            const int ix = t % m.ntx, iy = (t / m.ntx) % m.nty, iz = t / (m.ntx * m.nty);
-            if ((m.flags & (FLAG_PCC | FLAG_WIND)) == FLAG_PCC && (ix == 0 || iy == 0 || (m.dim == 3 && iz == 0)))
-                cand.push_back(EngineItem{(int32_t)r, t});
-        }
-        if ((m.flags & (FLAG_PCC | FLAG_WIND)) == FLAG_PCC) {
-            const int64_t nslots = (m.dim == 3) ? (int64_t)m.L * m.L : (int64_t)m.L;
-            for (int64_t k = 0; k * kPercChunk < nslots; ++k) perc.push_back(EngineItem{(int32_t)r, (int32_t)k});
+        if (!m.active) continue;
+        has2 = has2 || m.dim == 2;
+        has3 = has3 || m.dim == 3;
+        tiles += m.ntiles;
+    }
+    int ngroups = 1;
+    if (has2 && has3) {
+        ngroups = 2;
+        for (size_t r = 0; r < h->reps.size(); ++r)
+            if (h->reps[r].h.active) grp[r] = h->reps[r].h.dim == 2 ? 0 : 1;
+    } else {
+        std::vector<int> order;
+        for (size_t r = 0; r < h->reps.size(); ++r)
+            if (h->reps[r].h.active) order.push_back((int)r);
+        ngroups = (order.size() >= 2 && tiles >= 4 * (int64_t)device_cu_count()) ? 2 : 1;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return h->reps[x].h.N > h->reps[y].h.N; });
+        uint64_t load[2] = {0, 0};
+        for (int r : order) {
+            const int g = (ngroups == 2 && load[1] < load[0]) ? 1 : 0;
+            grp[r] = g;
+            load[g] += h->reps[r].h.N;
         }
     }
-    for (const EngineItem& it : items) n2 += h->reps[it.rep].h.dim == 2;
-    for (const EngineItem& it : cand) c2 += h->reps[it.rep].h.dim == 2;
+    std::vector<EngineItem> items, cand, perc, reps;
+    for (int g = 0; g < ngroups; ++g) {
+        BatchGroup& G = h->groups[g];
+        G.item0 = (int)items.size();
+        G.cand0 = (int)cand.size();
+        G.perc0 = (int)perc.size();
+        G.rep0 = (int)reps.size();
+        G.dim = 0;
+        for (size_t r = 0; r < h->reps.size(); ++r) {
+            if (grp[r] != g) continue;
+            const SwRep& m = h->reps[r].h;
+            G.dim = m.dim;
+            reps.push_back(EngineItem{(int32_t)r, 0});
+            for (int t = 0; t < m.ntiles; ++t) {
+                items.push_back(EngineItem{(int32_t)r, t});
+                const int ix = t % m.ntx, iy = (t / m.ntx) % m.nty, iz = t / (m.ntx * m.nty);
+                if ((m.flags & (FLAG_PCC | FLAG_WIND)) == FLAG_PCC && (ix == 0 || iy == 0 || (m.dim == 3 && iz == 0)))
+                    cand.push_back(EngineItem{(int32_t)r, t});
+            }
+            if ((m.flags & (FLAG_PCC | FLAG_WIND)) == FLAG_PCC) {
+                const int64_t nslots = (m.dim == 3) ? (int64_t)m.L * m.L : (int64_t)m.L;
+                for (int64_t k = 0; k * kPercChunk < nslots; ++k) perc.push_back(EngineItem{(int32_t)r, (int32_t)k});
+            }
+        }
+        G.nitems = (int)items.size() - G.item0;
+        G.ncand = (int)cand.size() - G.cand0;
+        G.nperc = (int)perc.size() - G.perc0;
+        G.nrep = (int)reps.size() - G.rep0;
+    }
+    h->ngroups = ngroups;
     const size_t nlist = items.size();
-    h->nitems2 = n2;
-    h->ncand2 = c2;
     h->ncand = (int)cand.size();
     h->nperc = (int)perc.size();
+    h->nreplist = (int)reps.size();
     items.insert(items.end(), cand.begin(), cand.end());
     items.insert(items.end(), perc.begin(), perc.end());
+    items.insert(items.end(), reps.begin(), reps.end());
     if (h->items_cap < items.size()) {
         dfree(h->items);
         h->items = nullptr;
@@ -626,6 +669,12 @@ static int build_items(sw_lattice* h)
     if (!items.empty()) {
         hipError_t e = hipMemcpy(h->items, items.data(), items.size() * sizeof(EngineItem), hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "uploading the engine work list");
+    }
+    if (ngroups == 2 && !h->side) {
+        hipError_t e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "creating the second batch stream");
     }
     h->nitems = (int)nlist;
     h->items_dirty = false;
@@ -719,10 +768,10 @@ int batched_sweep(sw_lattice* h, int32_t n)
         drop_graph(h);
         hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-        int lrc = launch_batch(variant, h->d_reps, (int)h->reps.size(), h->items, h->nitems, h->items + h->nitems,
-                               h->ncand, h->items + h->nitems + h->ncand, h->nperc, n, pcc_dims, any_series,
-                               (int)any_2d | ((int)any_3d << 1), h->nitems2, h->ncand2,
-                               grid, item_grid, h->merge_width, h->stream);
+        const EngineItem* cand = h->items + h->nitems;
+        int lrc = launch_batch(variant, h->d_reps, (int)h->reps.size(), h->items, h->nitems, cand, cand + h->ncand,
+                               cand + h->ncand + h->nperc, h->groups, h->ngroups, n, pcc_dims, any_series, grid,
+                               item_grid, h->merge_width, h->stream, h->side, h->fork_ev, h->join_ev);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(h->stream, &g);
         if (lrc || e != hipSuccess || !g) {
@@ -1179,6 +1228,12 @@ int sw_free(sw_lattice* h)
     dfree(h->d_reps);
     dfree(h->items);
     dfree(h->err);
+    if (h->side) {
+        (void)hipStreamSynchronize(h->side);
+        (void)hipStreamDestroy(h->side);
+    }
+    if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
+    if (h->join_ev) (void)hipEventDestroy(h->join_ev);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
     return SW_OK;

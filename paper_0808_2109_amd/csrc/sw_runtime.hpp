@@ -66,8 +66,11 @@ struct sw_lattice {
     int nitems = 0;
     int ncand = 0;                       // PCC tiles on a hyperplane x_a = 0 (after the work list)
     int nperc = 0;                       // PCC slot chunks (after the candidate list)
-    int nitems2 = 0;                     // 2D items at the front of the work list (3D ones follow)
-    int ncand2 = 0;                      // 2D items at the front of the candidate list
+    int nreplist = 0;                    // replicas of the groups (after the slot list)
+    sw::BatchGroup groups[2] = {};       // the batch's groups (one dimension each)
+    int ngroups = 0;
+    hipStream_t side = nullptr;          // second stream of a batch of two groups
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     bool items_dirty = true;
     int batch_per_cu = 0;               // workgroups per CU of the batched phase launches (0: one per tile)
     int merge_width = 0;                // threads per tile of the border merge (0: the tile's default, 64, 256)
