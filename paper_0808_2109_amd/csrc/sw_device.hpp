@@ -1221,7 +1221,6 @@ template <class C>
 struct K2Smem {
     uint32_t keys[K2Cfg<C>::H];
     uint32_t list[C::FT];      // keys of the unions to make (at most one per face site)
-    uint32_t xb[C::XW];        // the tile's crossing bits
     int cnt;
 };
 
@@ -1273,12 +1272,14 @@ __device__ void k2_tile(const SwRep& R, int t, K2Smem<C>& sm)
     using K = K2Width<C, NT>;
     const int tid = threadIdx.x, nt = NT;
     for (int i = tid; i < K::H; i += nt) sm.keys[i] = kK2Empty;
-    for (int i = tid; i < C::XW; i += nt) sm.xb[i] = R.xbits[(size_t)t * C::XW + i];
     if (tid == 0) sm.cnt = 0;
-    __syncthreads();
     const int ix = t % R.ntx, iy = (t / R.ntx) % R.nty, iz = t / (R.ntx * R.nty);
     const uint16_t* farf = R.face + (size_t)t * (2 * C::FT) + C::FT;
-    // 1) the labels at both ends of every open link of this thread's face sites
+    const uint32_t* xbt = R.xbits + (size_t)t * C::XW;
+    // 1) the labels at both ends of every open link of this thread's face
+    //    sites: the crossing bits and both face arrays are read together (the
+    //    labels of closed links are read too and dropped), so that one round
+    //    trip to memory brings all three
     uint32_t la[K::KF], lb[K::KF];
     int dk[K::KF];
     bool open[K::KF];
@@ -1292,18 +1293,18 @@ __device__ void k2_tile(const SwRep& R, int t, K2Smem<C>& sm)
             int d, fb, wbase;
             k2_face<C>(f, d, fb, wbase);
             dk[k] = d;
-            open[k] = (sm.xb[wbase + (fb >> 5)] >> (fb & 31)) & 1u;
-        }
-        if (open[k]) {
             int jx = ix, jy = iy, jz = iz;
-            if (dk[k] == 0) jx = (ix + 1 == R.ntx) ? 0 : ix + 1;
-            else if (dk[k] == 1) jy = (iy + 1 == R.nty) ? 0 : iy + 1;
+            if (d == 0) jx = (ix + 1 == R.ntx) ? 0 : ix + 1;
+            else if (d == 1) jy = (iy + 1 == R.nty) ? 0 : iy + 1;
             else jz = (iz + 1 == R.ntz) ? 0 : iz + 1;
             const int tn = jx + R.ntx * (jy + R.nty * jz);
+            const uint32_t xw = xbt[wbase + (fb >> 5)];
             la[k] = farf[f];
             lb[k] = R.face[(size_t)tn * (2 * C::FT) + f];
+            open[k] = (xw >> (fb & 31)) & 1u;
         }
     }
+    __syncthreads();   // the hash set is cleared
     // 2) the first link of each (face, near label, far label) triple; the
     //    labels are the ranks of the two tile roots among their tiles' border
     //    roots (with the topological rule, the tile-local labels)
