@@ -197,10 +197,18 @@ static int tune_batch(sw_lattice* h, int32_t sweeps, const char* cache_path)
             sw_lattice* s = nullptr;
             int rc = sw_init(ps.data(), (int32_t)ps.size(), -1, h->stream, &s);
             for (size_t r = 0; r < ps.size() && !rc; ++r) rc = sw_set_tile_shape(s, (int32_t)r, v);
-            for (size_t r = 0; r < ps.size() && !rc; ++r) rc = copy_state(s, (int)r, h, (int)r);
             if (!rc) s->mode = SW_MODE_BATCHED;
+            // every candidate starts from the batch's own state: the cost of a
+            // sweep changes as the replicas equilibrate, so candidates timed one
+            // after the other on a running copy would favour the later ones
+            auto restart = [&]() {
+                int e = 0;
+                for (size_t r = 0; r < ps.size() && !e; ++r) e = copy_state(s, (int)r, h, (int)r);
+                return e;
+            };
             for (int merge : {64, 256}) {
                 for (int per_cu : {0, 4, 8, 16}) {
+                    if (!rc) rc = restart();
                     if (rc) break;
                     s->batch_per_cu = per_cu;
                     s->merge_width = merge;
@@ -215,6 +223,7 @@ static int tune_batch(sw_lattice* h, int32_t sweeps, const char* cache_path)
                     }
                 }
             }
+            if (!rc) rc = restart();
             if (!rc) {
                 // the persistent engine, with as many workgroups as fit
                 s->batch_engine = SW_ENGINE_PERSISTENT;
