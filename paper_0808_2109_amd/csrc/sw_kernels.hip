@@ -340,7 +340,7 @@ __device__ __forceinline__ void item_range(int nitems, int& i0, int& i1)
 template <class C2, class C3, bool P2, bool P3>
 __device__ __forceinline__ void k1_item(const SwRep* reps, const EngineItem& item, int it, int n_sweeps, char* smem)
 {
-    const SwRep& R = reps[item.rep];
+    const SwRep R = reps[item.rep];   // a private copy: stores to the lattice's arrays cannot alias it
     uint32_t s;
     if (!rep_runs(R, it, n_sweeps, s)) return;
     int64_t* dst = nullptr;
@@ -397,7 +397,7 @@ __device__ __forceinline__ void k3a_item(const SwRep* reps, const EngineItem& it
 template <class C2, class C3>
 __device__ __forceinline__ void k3_item(const SwRep* reps, const EngineItem& item, int it, int n_sweeps, char* smem)
 {
-    const SwRep& R = reps[item.rep];
+    const SwRep R = reps[item.rep];   // a private copy: stores to the lattice's arrays cannot alias it
     uint32_t s;
     if (!rep_runs(R, it, n_sweeps, s)) return;
     if constexpr (std::is_same<C2, C3>::value) k3_tile<C2>(R, item.tile, s, *reinterpret_cast<K3Smem<C2>*>(smem));
